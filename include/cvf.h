@@ -1,0 +1,178 @@
+/*
+ * cvf.h -- C ABI of libcvf: Monte Carlo hot path of the CVF water model on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Model: Coronas, Vilanova, Franzese, "Efficient parallel algorithms for
+ * free-energy calculation of millions of water molecules in the fluid
+ * phases".  This library implements the model on a periodic L x L square
+ * lattice (the monolayer form of the model: 4 nearest neighbours, 4 bond
+ * indices per molecule, eta == 1):
+ *
+ *   state      {v_iso, sigma}            Sec. II.B (configuration)
+ *   enthalpy   H = U_LJ - J N_HB - J_sigma N_sigma + P V,
+ *              V = V_iso + v_HB N_HB     Eq. (1), Eq. (3), Table I
+ *   MC step    volume move, then the sigma update (Metropolis sweep or
+ *              Swendsen-Wang step)       Sec. II.B-II.D
+ *
+ * Layout (part of the ABI).  sigma is caller-owned device memory of 4*L*L
+ * bytes, plane-major as in Sec. II.C: sigma[a*N + c], N = L*L, cell
+ * c = x + L*y, arm a = 0:+x, 1:-x, 2:+y, 3:-y.  Arm a of cell c faces arm
+ * a^1 of the neighbour in direction a (periodic).  Values are 0..q-1.
+ *
+ * Randomness.  Philox4x32-10 keyed by the 64-bit seed, counter
+ * (index, step, sub, stream): a run is a pure function of (params, seed)
+ * and of the sequence of calls, independent of launch shape and of other
+ * jobs on the device.
+ *
+ * Conventions.
+ *  - Every function returns CVF_OK (0) or a negative CVF_E* code; nothing
+ *    aborts or throws across the ABI.  Validation failures leave the state
+ *    unchanged.  After CVF_EHIP the device state is undefined.
+ *  - Ownership: the caller allocates and frees all device memory (sigma and
+ *    the workspace); both must stay valid until cvf_destroy.  The library
+ *    allocates no device memory.  Host state is owned by the library and
+ *    freed by cvf_destroy.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  All
+ *    calls are asynchronous on that stream except cvf_observables and
+ *    cvf_kernel_times, which synchronise it.
+ *  - Threading: a cvf_state is not thread-safe; distinct states are
+ *    independent and may run concurrently on different streams.
+ */
+#ifndef CVF_H
+#define CVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define CVF_OK       0
+#define CVF_EINVAL  (-1)   /* invalid argument or parameter            */
+#define CVF_ENOMEM  (-2)   /* workspace smaller than required          */
+#define CVF_EHIP    (-3)   /* a HIP runtime call or launch failed      */
+#define CVF_ESTATE  (-4)   /* call not valid in the current state      */
+
+/* algorithm masks (cvf_workspace_bytes) */
+#define CVF_ALGO_METROPOLIS 1
+#define CVF_ALGO_SW         2
+
+/* cvf_params.flags */
+#define CVF_NO_VOLUME_MOVE  1u  /* skip the volume move of every step        */
+#define CVF_KEEP_SIGMA      2u  /* cvf_init keeps the caller's sigma          */
+
+/* Reduced units: energies in eps = 5.5 kJ/mol, volumes in v0 = r0^3
+ * (Table I).  beta = eps/(k_B T N_A); P is P r0^3 N_A / eps. */
+typedef struct cvf_params {
+    int32_t  L;        /* lattice side, even, 2 <= L <= 32766            */
+    int32_t  q;        /* states per bond index, 2..6 (paper: q = 6)     */
+    double   beta;     /* inverse reduced temperature, >= 0, finite      */
+    double   J;        /* covalent HB energy (Table I: 2.0)              */
+    double   Jsigma;   /* cooperative energy (Table I: 0.32), >= 0       */
+    double   P;        /* reduced pressure                               */
+    double   vHB;      /* volume per HB (Table I: 0.6)                   */
+    double   v_init;   /* initial v_iso/v0 per molecule, >= 1            */
+    double   dv_max;   /* half-width of the volume proposal, >= 0        */
+    uint64_t seed;     /* Philox key                                     */
+    uint32_t flags;    /* CVF_NO_VOLUME_MOVE | CVF_KEEP_SIGMA            */
+    uint32_t reserved; /* must be 0                                      */
+} cvf_params;
+
+/* Observables (Eq. (1), Eq. (3), Eq. (4)'s order parameter). */
+typedef struct cvf_obs {
+    int64_t step;           /* MC steps done                                   */
+    int64_t n_hb_raw;       /* facing pairs with equal sigma                    */
+    int64_t n_hb;           /* N_HB = theta * n_hb_raw (theta = [v < 2])        */
+    int64_t n_coop;         /* N_sigma: equal same-cell arm pairs               */
+    int64_t count[6];       /* N_q': sigma values in state q' (0 past q-1)      */
+    int64_t met_attempted;  /* Metropolis proposals                             */
+    int64_t met_accepted;
+    int64_t vol_attempted;  /* volume moves                                     */
+    int64_t vol_accepted;
+    double  v;              /* v_iso / v0                                       */
+    double  V;              /* N v + v_HB N_HB, units of v0                     */
+    double  H;              /* N u_LJ(v) - J N_HB - J_sigma N_sigma + P V       */
+    double  M;              /* max_q' N_q' / (4N)                               */
+    int32_t consistent;     /* 1 if the incremental counters equal a recount    */
+    int32_t reserved;
+} cvf_obs;
+
+typedef struct cvf_state cvf_state;
+
+/* Table I parameters at temperature T (K) and pressure P (MPa) in reduced
+ * units (SI-2019 N_A, k_B); L = 64, q = 6, v_init = 1.25, dv_max = 0.0125,
+ * seed = 1, flags = 0.  Host only.  CVF_EINVAL if out is NULL or T <= 0. */
+int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
+
+/* Device workspace needed for the algorithms in algo_mask: Metropolis
+ * needs a few KB; Swendsen-Wang adds 17 bytes per cell (labels of the 4N
+ * bond indices and one bond mask byte per cell).  Host only. */
+int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
+
+/* Create a chain.  d_sigma: 4*L*L bytes of device memory, layout above;
+ * filled from Philox stream INIT (sigma[a][c] = floor(w_a q / 2^32) of the
+ * block at counter (c, 0, 0, INIT)) unless CVF_KEEP_SIGMA.  d_work /
+ * work_bytes: caller-owned device workspace (256-byte aligned), at least
+ * cvf_workspace_bytes(p, CVF_ALGO_METROPOLIS); Swendsen-Wang steps need the
+ * larger size.  v = v_init, step = 0, counters from a full count.  *out
+ * receives the new state.  Asynchronous on stream. */
+int cvf_init(const cvf_params *p, uint8_t *d_sigma, void *d_work, size_t work_bytes,
+             void *stream, cvf_state **out);
+
+/* nsweeps MC steps, each a volume move (Sec. II.B step 1) followed by one
+ * checkerboard Metropolis sweep over every bond index (Sec. II.C): colour 0
+ * cells ((x+y) even) then colour 1, arms 0..3 in order inside a cell, each
+ * proposing a uniformly chosen different state and accepting it with
+ * min(1, exp(-beta dH)) through a 2^32-scaled table.  Asynchronous.
+ * nsweeps >= 0. */
+int cvf_metropolis_sweeps(cvf_state *st, int64_t nsweeps, void *stream);
+
+/* nsteps MC steps, each a volume move followed by one Swendsen-Wang step
+ * (Sec. II.D): bond activation, connected-component labelling to the
+ * minimum flat index of every cluster (the result Table II converges to),
+ * and a cluster-wide shift sigma <- (sigma + r) mod q with r drawn per
+ * cluster.  Needs the Swendsen-Wang workspace (CVF_ENOMEM otherwise) and
+ * J_sigma >= 0.  Asynchronous. */
+int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
+
+/* Recount the lattice, evaluate Eq. (1) and (3), and copy everything to
+ * *out.  Synchronises stream. */
+int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
+
+/* Copy the cluster labels of the last Swendsen-Wang step (4*L*L uint32,
+ * label[idx] = smallest flat index in idx's cluster) to device memory
+ * d_out.  CVF_ESTATE if no Swendsen-Wang step has run.  Asynchronous. */
+int cvf_labels(cvf_state *st, uint32_t *d_out, void *stream);
+
+/* Test hook: the host-computed acceptance tables of this chain.
+ * met[theta][dh+1][dc+3]: accept iff thr == 0xFFFFFFFF or word < thr.
+ * sw[0] cooperative bond threshold, sw[1], sw[2] covalent thresholds for
+ * theta = 0, 1 (bond iff word < thr, 64-bit compare).  Host only. */
+int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
+
+/* Kernel timing.  While enabled, every launch of the kernels of one kind
+ * is bracketed by HIP events on the caller's stream.  cvf_kernel_times
+ * synchronises those events and returns, for kind k, the number of
+ * launches and their mean duration in ms since timing was enabled. */
+#define CVF_K_VOLUME    0   /* volume move / counter fold          */
+#define CVF_K_MET_SWEEP 1   /* one checkerboard colour sweep       */
+#define CVF_K_SW_BONDS  2   /* bond activation + in-cell labels    */
+#define CVF_K_SW_UNION  3   /* covalent unions                     */
+#define CVF_K_SW_FLIP   4   /* flatten + cluster flip              */
+#define CVF_K_RECOUNT   5   /* lattice recount                     */
+#define CVF_K_COUNT     6
+int cvf_timing_enable(cvf_state *st, int enable);
+int cvf_kernel_times(cvf_state *st, int kind, int64_t *launches, double *mean_ms);
+
+/* Release the host state (device memory stays with the caller). */
+int cvf_destroy(cvf_state *st);
+
+/* Static description of an error code. */
+const char *cvf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CVF_H */

@@ -1,0 +1,373 @@
+// Host side of libcvf: parameter validation, host-computed tables, workspace
+// carving, step sequencing on the caller's stream, kernel timing.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "cvf_internal.h"
+
+using namespace cvf;
+
+struct cvf_state {
+    cvf_params p;
+    uint8_t* sigma;
+    char* work;
+    size_t work_bytes;
+    bool has_sw;
+    uint32_t N;
+    DevState* dst;
+    int64_t* slots;
+    DevTables* dtab;
+    DevObs* dobs;
+    uint32_t* label;
+    uint8_t* mask;
+    DevTables htab;          // host copy (source of the init copy, test hook)
+    LatticeArgs la;
+    VolArgs va;
+    bool timing;
+    std::vector<hipEvent_t> ev[CVF_K_COUNT];   // start/stop pairs pending
+    double ms[CVF_K_COUNT];
+    int64_t launches[CVF_K_COUNT];
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int validate(const cvf_params* p)
+{
+    if (!p) return CVF_EINVAL;
+    if (p->L < 2 || p->L > 32766 || (p->L & 1)) return CVF_EINVAL;
+    if (p->q < 2 || p->q > 6) return CVF_EINVAL;
+    if (!(p->beta >= 0.0) || !isfinite(p->beta)) return CVF_EINVAL;
+    if (!isfinite(p->J) || !isfinite(p->Jsigma) || !isfinite(p->P) || !isfinite(p->vHB)) return CVF_EINVAL;
+    if (!(p->v_init >= 1.0) || !isfinite(p->v_init)) return CVF_EINVAL;
+    if (!(p->dv_max >= 0.0) || !isfinite(p->dv_max)) return CVF_EINVAL;
+    if (p->flags & ~(CVF_NO_VOLUME_MOVE | CVF_KEEP_SIGMA)) return CVF_EINVAL;
+    if (p->reserved != 0) return CVF_EINVAL;
+    return CVF_OK;
+}
+
+size_t sw_bytes(uint64_t N) { return align256(4 * N * sizeof(uint32_t)) + align256(N); }
+
+// Number of integer points on the circle i^2 + j^2 = m, counted over the
+// first quadrant (i > 0, j >= 0) and multiplied by the 4 rotations.
+double lattice_points(int m)
+{
+    if (m == 0) return 1.0;
+    int n = 0;
+    for (int i = 1; i * i <= m; ++i)
+        for (int j = 0; i * i + j * j <= m; ++j)
+            if (i * i + j * j == m) ++n;
+    return 4.0 * n;
+}
+
+// Acceptance tables, Sec. II.C / II.D with Eq. (3): dH = -theta J_eff dh -
+// J_sigma dc for one bond-index change; bond probability 1 - exp(-beta|J|).
+void build_tables(const cvf_params* p, DevTables* t)
+{
+    memset(t, 0, sizeof(*t));
+    const double Jeff = p->J - p->P * p->vHB;
+    for (int th = 0; th < 2; ++th)
+        for (int dh = -1; dh <= 1; ++dh)
+            for (int dc = -3; dc <= 3; ++dc) {
+                const double dH = -((double)th * Jeff * (double)dh) - p->Jsigma * (double)dc;
+                uint32_t thr = 0xFFFFFFFFu;
+                if (dH > 0.0) {
+                    const double acc = exp(-p->beta * dH);
+                    if (acc < 1.0) {
+                        const double f = floor(acc * 4294967296.0);
+                        thr = f > 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)f;
+                    }
+                }
+                t->met[th][(dh + 1) * 7 + dc + 3] = thr;
+            }
+    const double xs = p->beta * p->Jsigma;
+    t->sw[0] = xs > 0.0 ? (uint64_t)floor(-expm1(-xs) * 4294967296.0) : 0;
+    t->sw[1] = 0;
+    const double xe = p->beta * fabs(Jeff);
+    t->sw[2] = xe > 0.0 ? (uint64_t)floor(-expm1(-xe) * 4294967296.0) : 0;
+    for (int m = 0; m < 40; ++m) t->r2[m] = m <= 36 ? lattice_points(m) : 0.0;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? CVF_OK : CVF_EHIP; }
+
+void timing_begin(cvf_state* st, int kind, hipStream_t s)
+{
+    if (!st->timing) return;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return;
+    }
+    (void)hipEventRecord(e0, s);
+    st->ev[kind].push_back(e0);
+    st->ev[kind].push_back(e1);
+}
+
+void timing_end(cvf_state* st, int kind, hipStream_t s)
+{
+    if (!st->timing || st->ev[kind].empty()) return;
+    (void)hipEventRecord(st->ev[kind].back(), s);
+}
+
+int drain_timing(cvf_state* st)
+{
+    int rc = CVF_OK;
+    for (int k = 0; k < CVF_K_COUNT; ++k) {
+        std::vector<hipEvent_t>& v = st->ev[k];
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventSynchronize(v[i + 1]) != hipSuccess || hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
+                rc = CVF_EHIP;
+            st->ms[k] += ms;
+            st->launches[k] += 1;
+        }
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
+    return rc;
+}
+
+#define TIMED(kind, call)                           \
+    do {                                            \
+        timing_begin(st, kind, s);                  \
+        hipError_t e_ = (call);                     \
+        timing_end(st, kind, s);                    \
+        if (e_ != hipSuccess) return CVF_EHIP;      \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params* out)
+{
+    if (!out || !(T_kelvin > 0.0) || !isfinite(T_kelvin) || !isfinite(P_MPa)) return CVF_EINVAL;
+    const double N_A = 6.02214076e23;   // 1/mol (SI 2019, exact)
+    const double k_B = 1.380649e-23;    // J/K (SI 2019, exact)
+    const double eps = 5.5e3;           // J/mol, Table I
+    const double r0 = 2.9e-10;          // m, Table I
+    const double R = N_A * k_B;
+    memset(out, 0, sizeof(*out));
+    out->L = 64;
+    out->q = 6;
+    out->beta = eps / (R * T_kelvin);
+    out->J = 4.0 * 0.5;                 // J / (4 eps) = 0.5
+    out->Jsigma = 4.0 * 0.08;           // J_sigma / (4 eps) = 0.08
+    out->P = ((P_MPa * 1.0e6) * (r0 * r0 * r0)) * N_A / eps;
+    out->vHB = 0.6;                     // v_HB = 0.6 v0
+    out->v_init = 1.25;
+    out->dv_max = 0.01 * 1.25;
+    out->seed = 1;
+    out->flags = 0;
+    return CVF_OK;
+}
+
+int cvf_workspace_bytes(const cvf_params* p, int algo_mask, size_t* bytes)
+{
+    if (!bytes || (algo_mask & ~(CVF_ALGO_METROPOLIS | CVF_ALGO_SW))) return CVF_EINVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    const uint64_t N = (uint64_t)p->L * (uint64_t)p->L;
+    size_t b = kBaseBytes;
+    if (algo_mask & CVF_ALGO_SW) b += sw_bytes(N);
+    *bytes = b;
+    return CVF_OK;
+}
+
+int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_bytes, void* stream,
+             cvf_state** out)
+{
+    if (!out || !d_sigma || !d_work) return CVF_EINVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (((uintptr_t)d_work & 255) != 0) return CVF_EINVAL;
+    if (work_bytes < kBaseBytes) return CVF_ENOMEM;
+    cvf_state* st = new (std::nothrow) cvf_state();
+    if (!st) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    st->p = *p;
+    st->sigma = d_sigma;
+    st->work = (char*)d_work;
+    st->work_bytes = work_bytes;
+    st->N = (uint32_t)p->L * (uint32_t)p->L;
+    st->has_sw = work_bytes >= kBaseBytes + sw_bytes(st->N);
+    st->dst = (DevState*)(st->work + kOffState);
+    st->slots = (int64_t*)(st->work + kOffSlots);
+    st->dtab = (DevTables*)(st->work + kOffTables);
+    st->dobs = (DevObs*)(st->work + kOffObs);
+    st->label = st->has_sw ? (uint32_t*)(st->work + kBaseBytes) : nullptr;
+    st->mask = st->has_sw ? (uint8_t*)(st->work + kBaseBytes + align256(4ull * st->N * sizeof(uint32_t))) : nullptr;
+    build_tables(p, &st->htab);
+
+    const double Jeff = p->J - p->P * p->vHB;
+    const uint32_t qm1 = (uint32_t)p->q - 1;
+    const uint64_t dm = (1ull << 32) / qm1, dq = (1ull << 32) / (uint32_t)p->q;
+    LatticeArgs& a = st->la;
+    a.sigma = d_sigma;
+    a.st = st->dst;
+    a.slots = st->slots;
+    a.tab = st->dtab;
+    a.label = st->label;
+    a.mask = st->mask;
+    a.L = (uint32_t)p->L;
+    a.N = st->N;
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.q = (uint32_t)p->q;
+    a.met_lim = (uint32_t)(qm1 * dm - 1);
+    a.flip_lim = (uint32_t)((uint64_t)p->q * dq - 1);
+    a.jeff_sign = Jeff > 0.0 ? 1 : (Jeff < 0.0 ? -1 : 0);
+    a.met_invd = 1.0 / (double)dm;
+    a.flip_invd = 1.0 / (double)dq;
+
+    VolArgs& v = st->va;
+    v.st = st->dst;
+    v.slots = st->slots;
+    v.tab = st->dtab;
+    v.Nd = (double)st->N;
+    v.beta = p->beta;
+    v.J = p->J;
+    v.P = p->P;
+    v.vHB = p->vHB;
+    v.dv_max = p->dv_max;
+    v.key0 = a.key0;
+    v.key1 = a.key1;
+    v.met_att_add = 0;
+    v.mode = kVolMet;
+    v.do_volume = (p->flags & CVF_NO_VOLUME_MOVE) ? 0 : 1;
+
+    hipError_t e = hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, p->v_init, s);
+    if (e == hipSuccess && !(p->flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(a, s);
+    if (e == hipSuccess) e = launch_recount(a, st->slots, kSlots, 0, s);
+    if (e != hipSuccess) {
+        delete st;
+        return CVF_EHIP;
+    }
+    *out = st;
+    return CVF_OK;
+}
+
+int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
+{
+    if (!st || nsweeps < 0) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    VolArgs v = st->va;
+    v.mode = kVolMet;
+    v.met_att_add = 4 * (int64_t)st->N;
+    for (int64_t i = 0; i < nsweeps; ++i) {
+        TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 0, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 1, s));
+    }
+    return CVF_OK;
+}
+
+int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
+{
+    if (!st || nsteps < 0) return CVF_EINVAL;
+    if (!st->has_sw) return CVF_ENOMEM;
+    if (!(st->p.Jsigma >= 0.0)) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    VolArgs v = st->va;
+    v.mode = kVolSw;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        TIMED(CVF_K_SW_BONDS, launch_sw_bonds(st->la, s));
+        TIMED(CVF_K_SW_UNION, launch_sw_union(st->la, s));
+        TIMED(CVF_K_SW_FLIP, launch_sw_flip(st->la, s));
+        TIMED(CVF_K_RECOUNT, launch_recount(st->la, st->slots, kSlots, 0, s));
+    }
+    return CVF_OK;
+}
+
+int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
+{
+    if (!st || !out) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    VolArgs v = st->va;
+    v.mode = kVolFold;
+    hipError_t e = launch_volume(v, s);
+    if (e == hipSuccess) e = launch_obs_zero(st->dobs, s);
+    if (e == hipSuccess) e = launch_recount(st->la, st->dobs->acc, 1, 1, s);
+    if (e == hipSuccess)
+        e = launch_obs_final(st->dobs, st->dst, st->dtab, (double)st->N, st->p.J, st->p.Jsigma, st->p.P,
+                             st->p.vHB, s);
+    cvf_obs tmp;
+    if (e == hipSuccess) e = hipMemcpyAsync(&tmp, &st->dobs->out, sizeof(cvf_obs), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return CVF_EHIP;
+    *out = tmp;
+    return CVF_OK;
+}
+
+int cvf_labels(cvf_state* st, uint32_t* d_out, void* stream)
+{
+    if (!st || !d_out) return CVF_EINVAL;
+    if (!st->has_sw) return CVF_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t done = 0;
+    hipError_t e = hipMemcpyAsync(&done, &st->dst->sw_done, sizeof(done), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return CVF_EHIP;
+    if (!done) return CVF_ESTATE;
+    return hip_status(hipMemcpyAsync(d_out, st->label, 4ull * st->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+}
+
+int cvf_tables(const cvf_state* st, uint32_t met[2][3][7], uint64_t sw[3])
+{
+    if (!st || !met || !sw) return CVF_EINVAL;
+    for (int th = 0; th < 2; ++th)
+        for (int i = 0; i < 21; ++i) met[th][i / 7][i % 7] = st->htab.met[th][i];
+    for (int i = 0; i < 3; ++i) sw[i] = st->htab.sw[i];
+    return CVF_OK;
+}
+
+int cvf_timing_enable(cvf_state* st, int enable)
+{
+    if (!st) return CVF_EINVAL;
+    int rc = drain_timing(st);
+    for (int k = 0; k < CVF_K_COUNT; ++k) {
+        st->ms[k] = 0.0;
+        st->launches[k] = 0;
+    }
+    st->timing = enable != 0;
+    return rc;
+}
+
+int cvf_kernel_times(cvf_state* st, int kind, int64_t* launches, double* mean_ms)
+{
+    if (!st || kind < 0 || kind >= CVF_K_COUNT || !launches || !mean_ms) return CVF_EINVAL;
+    int rc = drain_timing(st);
+    *launches = st->launches[kind];
+    *mean_ms = st->launches[kind] ? st->ms[kind] / (double)st->launches[kind] : 0.0;
+    return rc;
+}
+
+int cvf_destroy(cvf_state* st)
+{
+    if (!st) return CVF_EINVAL;
+    drain_timing(st);
+    delete st;
+    return CVF_OK;
+}
+
+const char* cvf_strerror(int code)
+{
+    switch (code) {
+    case CVF_OK: return "ok";
+    case CVF_EINVAL: return "invalid argument";
+    case CVF_ENOMEM: return "workspace too small";
+    case CVF_EHIP: return "HIP runtime error";
+    case CVF_ESTATE: return "invalid state for this call";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal definitions shared by the host API and the HIP kernels of libcvf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cvf.h"
+
+namespace cvf {
+
+// Philox stream ids (fourth counter word): one per kind of random decision.
+constexpr uint32_t kStreamInit = 0;   // initial configuration
+constexpr uint32_t kStreamVol = 1;    // volume move
+constexpr uint32_t kStreamMet = 2;    // Metropolis proposal + acceptance
+constexpr uint32_t kStreamSwb = 3;    // Swendsen-Wang bond activation
+constexpr uint32_t kStreamSwf = 4;    // Swendsen-Wang cluster shift
+
+// Per-workgroup partial sums are spread over this many int64 slots so that
+// same-address atomics do not serialise; the volume kernel folds them.
+constexpr int kSlots = 64;
+
+// Mutable per-chain scalars, at offset 0 of the workspace.
+struct DevState {
+    int64_t t_next;          // index of the next MC step
+    int64_t n_hb_raw;        // incremental totals (after folding the slots)
+    int64_t n_coop;
+    int64_t met_att, met_acc, vol_att, vol_acc;
+    double v;                // v_iso / v0
+    uint32_t t_cur;          // step being executed (Philox counter word 1)
+    int32_t theta;           // 1 liquid (v < 2), 0 gas
+    int32_t sw_done;         // a Swendsen-Wang step has produced labels
+    int32_t pad_;
+};
+
+// Host-computed constants copied to the workspace at init.
+struct DevTables {
+    uint32_t met[2][21];     // Metropolis thresholds [theta][(dh+1)*7 + dc+3]
+    uint32_t pad_[2];
+    uint64_t sw[3];          // SW thresholds: cooperative, covalent theta=0, theta=1
+    double r2[40];           // lattice-point counts r2(m), m = 0..36
+};
+
+// Observable accumulators + the final record copied to the host.
+struct DevObs {
+    int64_t acc[8];          // recount: n_hb_raw, n_coop, count[0..5]
+    cvf_obs out;
+};
+
+// Workspace layout (byte offsets, all 256-aligned).
+constexpr size_t kOffState = 0;
+constexpr size_t kOffSlots = 256;
+constexpr size_t kOffTables = kOffSlots + 3 * kSlots * sizeof(int64_t);   // 1792
+constexpr size_t kOffObs = kOffTables + 768;                                // 2560
+constexpr size_t kBaseBytes = kOffObs + 512;                                // 3072
+
+static_assert(sizeof(DevState) <= 256, "DevState");
+static_assert(sizeof(DevTables) <= 768, "DevTables");
+static_assert(sizeof(DevObs) <= 512, "DevObs");
+
+// Arguments common to the lattice kernels (passed by value).
+struct LatticeArgs {
+    uint8_t* sigma;
+    DevState* st;
+    int64_t* slots;
+    const DevTables* tab;
+    uint32_t* label;         // Swendsen-Wang only
+    uint8_t* mask;           // Swendsen-Wang only
+    uint32_t L, N;           // side, L*L
+    uint32_t key0, key1;     // Philox key (seed)
+    uint32_t q;
+    uint32_t met_lim;        // largest proposal word that is not NULL (q-1 states)
+    uint32_t flip_lim;       // same for the q-state cluster shift
+    int32_t jeff_sign;       // sign of J_eff = J - P v_HB
+    double met_invd;         // 1 / floor(2^32/(q-1))
+    double flip_invd;        // 1 / floor(2^32/q)
+};
+
+struct VolArgs {
+    DevState* st;
+    int64_t* slots;
+    const DevTables* tab;
+    double Nd, beta, J, P, vHB, dv_max;
+    uint32_t key0, key1;
+    int64_t met_att_add;     // Metropolis proposals per sweep (4N) or 0
+    int32_t mode;            // 0: Metropolis step, 1: SW step, 2: fold only
+    int32_t do_volume;
+};
+
+enum VolMode { kVolMet = 0, kVolSw = 1, kVolFold = 2 };
+
+// Launchers (cvf_kernels.hip).  Each returns the launch status.
+hipError_t launch_state_init(DevState* st, int64_t* slots, double v_init, hipStream_t s);
+hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_volume(const VolArgs& a, hipStream_t s);
+hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
+hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, hipStream_t s);
+hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
+hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
+                            double Jsigma, double P, double vHB, hipStream_t s);
+hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
+
+}  // namespace cvf

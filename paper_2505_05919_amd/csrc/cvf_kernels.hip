@@ -1,0 +1,557 @@
+// HIP kernels of libcvf for gfx950 (MI355X).
+//
+// The lattice kernels are integer-only: uint8 bond indices, uint32 Philox
+// words and thresholds, int32 per-lane deltas reduced across the wavefront
+// and the workgroup, int64 atomics into spread slots.  The single-wave
+// volume kernel is the only floating-point code (FP64, no contraction).
+#include "cvf_internal.h"
+
+namespace cvf {
+namespace {
+
+constexpr int kBlock = 256;           // 4 wavefronts of 64
+constexpr int kMaxBlocks = 8192;      // 256 CUs x 8 waves/SIMD x 4 SIMDs / 4 waves
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The key words are
+// wave-uniform (the chain's seed), so the key schedule lives in SGPRs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// floor(j / d) and j mod d for j < 2^32, d < 2^15: one FP64 multiply by the
+// reciprocal is at most one too small, never too large; one correction.
+__device__ __forceinline__ uint32_t divmod(uint32_t j, uint32_t d, double inv, uint32_t& rem)
+{
+    uint32_t qt = (uint32_t)((double)j * inv);
+    uint32_t r = j - qt * d;
+    if (r >= d) {
+        ++qt;
+        r -= d;
+    }
+    rem = r;
+    return qt;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV int32 values over the workgroup and add them (as int64) to
+// dst[i * stride] (one atomic per value per workgroup).
+template <int NV>
+__device__ __forceinline__ void block_add(const int (&v)[NV], int64_t* dst, int stride)
+{
+    __shared__ int part[NV][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int s = wave_sum(v[i]);
+        if (lane == 0) part[i][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        int64_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += part[threadIdx.x][w];
+        if (s) atomicAdd((unsigned long long*)(dst + (size_t)threadIdx.x * stride), (unsigned long long)s);
+    }
+}
+
+inline unsigned grid_for(uint64_t work)
+{
+    uint64_t b = (work + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------
+// Lennard-Jones lattice energy per molecule (Sec. II.A): hard core r0,
+// cutoff 6 r0, square lattice of spacing sqrt(v) r0.  Same operation order as
+// the definition: ascending shells m = |n|^2, s = (v m)^-3, 2 sum r2 (s^2-s).
+// ---------------------------------------------------------------------------
+__device__ double lj_energy(double v, const double* r2)
+{
+    double s = 0.0;
+    for (int m = 1; v * (double)m <= 36.0; ++m) {
+        const double d2 = v * (double)m;
+        const double s6 = 1.0 / (d2 * d2 * d2);
+        s = s + r2[m] * (s6 * s6 - s6);
+    }
+    return 2.0 * s;
+}
+
+// ---------------------------------------------------------------------------
+// State initialisation.
+// ---------------------------------------------------------------------------
+__global__ void state_init_kernel(DevState* st, int64_t* slots, double v_init)
+{
+    const int i = threadIdx.x;
+    for (int k = i; k < 3 * kSlots; k += blockDim.x) slots[k] = 0;
+    if (i == 0) {
+        st->t_next = 0;
+        st->n_hb_raw = 0;
+        st->n_coop = 0;
+        st->met_att = st->met_acc = st->vol_att = st->vol_acc = 0;
+        st->v = v_init;
+        st->t_cur = 0;
+        st->theta = v_init < 2.0 ? 1 : 0;
+        st->sw_done = 0;
+        st->pad_ = 0;
+    }
+}
+
+// sigma[a][c] = floor(w_a q / 2^32), (w0..w3) = Philox(c, 0, 0, INIT).
+__global__ __launch_bounds__(kBlock) void sigma_init_kernel(LatticeArgs a)
+{
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        const uint4 w = philox(c, 0u, 0u, kStreamInit, a.key0, a.key1);
+        a.sigma[c] = (uint8_t)(((uint64_t)w.x * a.q) >> 32);
+        a.sigma[(size_t)a.N + c] = (uint8_t)(((uint64_t)w.y * a.q) >> 32);
+        a.sigma[2 * (size_t)a.N + c] = (uint8_t)(((uint64_t)w.z * a.q) >> 32);
+        a.sigma[3 * (size_t)a.N + c] = (uint8_t)(((uint64_t)w.w * a.q) >> 32);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Volume move + counter fold: one wavefront.  Folds the per-workgroup slots
+// of the previous sigma update into the totals, opens step t, and performs
+// the Metropolis move of v_iso (Sec. II.B step 1) with the full dH of
+// Eq. (1) and (3):  N (u(v') - u(v)) + P N (v' - v)
+//                   + (theta(v') - theta(v)) (P v_HB - J) N_HB_raw.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void volume_kernel(VolArgs a)
+{
+    const int lane = threadIdx.x;
+    int64_t hb = 0, co = 0, ac = 0;
+    for (int i = lane; i < kSlots; i += 64) {
+        hb += a.slots[i];
+        co += a.slots[kSlots + i];
+        ac += a.slots[2 * kSlots + i];
+        a.slots[i] = 0;
+        a.slots[kSlots + i] = 0;
+        a.slots[2 * kSlots + i] = 0;
+    }
+    hb = wave_sum64(hb);
+    co = wave_sum64(co);
+    ac = wave_sum64(ac);
+    if (lane != 0) return;
+    DevState* st = a.st;
+    st->n_hb_raw += hb;
+    st->n_coop += co;
+    st->met_acc += ac;
+    if (a.mode == kVolFold) return;
+    const uint32_t t = (uint32_t)st->t_next;
+    st->t_cur = t;
+    st->t_next += 1;
+    st->met_att += a.met_att_add;
+    if (a.do_volume) {
+        const uint4 w = philox(0u, t, 0u, kStreamVol, a.key0, a.key1);
+        st->vol_att += 1;
+        const double u = (double)((int64_t)2 * (int64_t)w.x + 1 - 4294967296LL) * (1.0 / 4294967296.0);
+        const double v0 = st->v;
+        const double v1 = v0 + a.dv_max * u;
+        if (v1 >= 1.0) {
+            const int th0 = st->theta;
+            const int th1 = v1 < 2.0 ? 1 : 0;
+            const double dH = (a.Nd * (lj_energy(v1, a.tab->r2) - lj_energy(v0, a.tab->r2)))
+                            + ((a.P * a.Nd) * (v1 - v0))
+                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)st->n_hb_raw);
+            bool acc = dH <= 0.0;
+            if (!acc) acc = ((double)w.y + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
+            if (acc) {
+                st->v = v1;
+                st->theta = th1;
+                st->vol_acc += 1;
+            }
+        }
+    }
+    if (a.mode == kVolSw) {         // the SW step ends with a full recount
+        st->n_hb_raw = 0;
+        st->n_coop = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Checkerboard Metropolis: every cell of one colour, arms 0..3 in order
+// (Sec. II.C).  Cells of one colour share no interaction: arm a of c only
+// couples to the other arms of c (J_sigma) and to arm a^1 of the neighbour
+// in direction a (J_eff), which has the other colour.
+// ---------------------------------------------------------------------------
+struct MetCtx {
+    const uint32_t* tbl;     // LDS copy of the thresholds for this theta
+    uint32_t q, lim;
+    double invd;
+};
+
+__device__ __forceinline__ void met_update(const MetCtx& m, int& sa, int facing, int b1, int b2, int b3,
+                                           uint32_t prop, uint32_t accw, int& dhb, int& dco, int& nacc)
+{
+    const bool valid = prop <= m.lim;                         // NULL proposal otherwise
+    const int k = (int)((double)prop * m.invd);               // floor(prop / floor(2^32/(q-1)))
+    int sn = sa + 1 + k;
+    sn = sn >= (int)m.q ? sn - (int)m.q : sn;
+    const int dh = (sn == facing) - (sa == facing);
+    const int dc = (sn == b1) + (sn == b2) + (sn == b3) - (sa == b1) - (sa == b2) - (sa == b3);
+    const uint32_t thr = m.tbl[(dh + 1) * 7 + dc + 3];
+    // accept iff thr == 2^32-1 or accw < thr  <=>  min(accw, 2^32-2) < thr
+    const bool acc = valid && (min(accw, 0xFFFFFFFEu) < thr);
+    if (acc) {
+        sa = sn;
+        dhb += dh;
+        dco += dc;
+        nacc += 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void met_colour_kernel(LatticeArgs a, int colour)
+{
+    __shared__ uint32_t tbl[21];
+    const int theta = a.st->theta;
+    const uint32_t t = a.st->t_cur;
+    if (threadIdx.x < 21) tbl[threadIdx.x] = a.tab->met[theta][threadIdx.x];
+    __syncthreads();
+    const MetCtx m{tbl, a.q, a.met_lim, a.met_invd};
+    const uint32_t L = a.L, half = L >> 1, ncol = a.N >> 1;
+    const size_t N = a.N;
+    const double inv_half = 1.0 / (double)half;
+    uint8_t* __restrict__ s = a.sigma;
+    int dhb = 0, dco = 0, nacc = 0;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < ncol; j += gridDim.x * kBlock) {
+        uint32_t xh;
+        const uint32_t y = divmod(j, half, inv_half, xh);
+        const uint32_t x = 2 * xh + ((y + colour) & 1);
+        const uint32_t row = y * L;
+        const uint32_t c = x + row;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+        const uint32_t rp = (y + 1 == L) ? 0 : row + L;
+        const uint32_t rm = (y == 0) ? (L - 1) * L : row - L;
+        int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
+        const int f0 = s[N + xp + row];          // arm 1 of the +x neighbour
+        const int f1 = s[xm + row];              // arm 0 of the -x neighbour
+        const int f2 = s[3 * N + x + rp];        // arm 3 of the +y neighbour
+        const int f3 = s[2 * N + x + rm];        // arm 2 of the -y neighbour
+        uint4 w = philox(c, t, 0u, kStreamMet, a.key0, a.key1);
+        met_update(m, s0, f0, s1, s2, s3, w.x, w.y, dhb, dco, nacc);
+        met_update(m, s1, f1, s0, s2, s3, w.z, w.w, dhb, dco, nacc);
+        w = philox(c, t, 1u, kStreamMet, a.key0, a.key1);
+        met_update(m, s2, f2, s0, s1, s3, w.x, w.y, dhb, dco, nacc);
+        met_update(m, s3, f3, s0, s1, s2, w.z, w.w, dhb, dco, nacc);
+        s[c] = (uint8_t)s0;
+        s[N + c] = (uint8_t)s1;
+        s[2 * N + c] = (uint8_t)s2;
+        s[3 * N + c] = (uint8_t)s3;
+    }
+    const int v[3] = {dhb, dco, nacc};
+    block_add<3>(v, a.slots + (blockIdx.x & (kSlots - 1)), kSlots);
+}
+
+// ---------------------------------------------------------------------------
+// Full recount of N_HB_raw, N_sigma (and optionally N_q').
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts)
+{
+    const uint32_t L = a.L;
+    const size_t N = a.N;
+    const double inv_L = 1.0 / (double)L;
+    const uint8_t* __restrict__ s = a.sigma;
+    int hb = 0, co = 0;
+    int cnt[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        uint32_t x;
+        const uint32_t y = divmod(c, L, inv_L, x);
+        const uint32_t row = y * L;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        const uint32_t rp = (y + 1 == L) ? 0 : row + L;
+        const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
+        hb += (s0 == s[N + xp + row]) + (s2 == s[3 * N + x + rp]);
+        co += (s0 == s1) + (s0 == s2) + (s0 == s3) + (s1 == s2) + (s1 == s3) + (s2 == s3);
+        if (with_counts) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) cnt[k] += (s0 == k) + (s1 == k) + (s2 == k) + (s3 == k);
+        }
+    }
+    if (with_counts) {
+        const int v[8] = {hb, co, cnt[0], cnt[1], cnt[2], cnt[3], cnt[4], cnt[5]};
+        block_add<8>(v, out, 1);
+    } else {
+        const int v[2] = {hb, co};
+        block_add<2>(v, out + (blockIdx.x & (spread - 1)), spread);
+    }
+}
+
+__global__ void obs_zero_kernel(DevObs* o)
+{
+    if (threadIdx.x < 8) o->acc[threadIdx.x] = 0;
+}
+
+// Observables from the recount and the chain scalars (Eq. (1), (3)).
+__global__ void obs_final_kernel(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
+                                 double Jsigma, double P, double vHB)
+{
+    if (threadIdx.x != 0) return;
+    cvf_obs& r = o->out;
+    r.step = st->t_next;
+    r.n_hb_raw = o->acc[0];
+    r.n_hb = st->theta ? o->acc[0] : 0;
+    r.n_coop = o->acc[1];
+    int64_t mx = 0;
+    for (int k = 0; k < 6; ++k) {
+        r.count[k] = o->acc[2 + k];
+        mx = r.count[k] > mx ? r.count[k] : mx;
+    }
+    r.met_attempted = st->met_att;
+    r.met_accepted = st->met_acc;
+    r.vol_attempted = st->vol_att;
+    r.vol_accepted = st->vol_acc;
+    r.v = st->v;
+    r.V = (Nd * st->v) + (vHB * (double)r.n_hb);
+    r.H = (((Nd * lj_energy(st->v, tab->r2)) - (J * (double)r.n_hb)) - (Jsigma * (double)r.n_coop)) + (P * r.V);
+    r.M = (double)mx / (4.0 * Nd);
+    r.consistent = (st->n_hb_raw == o->acc[0] && st->n_coop == o->acc[1]) ? 1 : 0;
+    r.reserved = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Swendsen-Wang (Sec. II.D).
+// Bond mask per cell: bit 0 covalent +x (arm 0 of c, arm 1 of c+x), bit 1
+// covalent +y (arm 2 of c, arm 3 of c+y), bits 2..7 cooperative pairs
+// (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).  Link l uses word l of
+// Philox(c, t, 0, SWB) for l < 4 and word l-4 of Philox(c, t, 1, SWB).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool below(uint32_t w, uint64_t thr) { return (uint64_t)w < thr; }
+
+// In-cell components of the 4 arms for each of the 64 cooperative masks:
+// 2 bits per arm = smallest arm index of its component.
+__device__ void build_incell_lut(uint8_t* lut)
+{
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
+    if (threadIdx.x < 64) {
+        const int m = threadIdx.x;
+        int lab[4] = {0, 1, 2, 3};
+        for (int it = 0; it < 3; ++it)
+            for (int l = 0; l < 6; ++l)
+                if (m >> l & 1) {
+                    const int mn = min(lab[pa[l]], lab[pb[l]]);
+                    lab[pa[l]] = mn;
+                    lab[pb[l]] = mn;
+                }
+        lut[m] = (uint8_t)(lab[0] | lab[1] << 2 | lab[2] << 4 | lab[3] << 6);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sw_bonds_kernel(LatticeArgs a)
+{
+    __shared__ uint8_t lut[64];
+    build_incell_lut(lut);
+    __syncthreads();
+    const uint32_t t = a.st->t_cur;
+    const int theta = a.st->theta;
+    const uint64_t thr_s = a.tab->sw[0];
+    const uint64_t thr_e = a.tab->sw[1 + theta];
+    const bool cov_on = theta == 1 && a.jeff_sign != 0;
+    const uint32_t L = a.L;
+    const size_t N = a.N;
+    const double inv_L = 1.0 / (double)L;
+    const uint8_t* __restrict__ s = a.sigma;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        uint32_t x;
+        const uint32_t y = divmod(c, L, inv_L, x);
+        const uint32_t row = y * L;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        const uint32_t rp = (y + 1 == L) ? 0 : row + L;
+        const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
+        const int f0 = s[N + xp + row];
+        const int f2 = s[3 * N + x + rp];
+        const uint4 w0 = philox(c, t, 0u, kStreamSwb, a.key0, a.key1);
+        const uint4 w1 = philox(c, t, 1u, kStreamSwb, a.key0, a.key1);
+        uint32_t m = 0;
+        if (cov_on) {
+            const bool e0 = (s0 == f0) == (a.jeff_sign > 0);
+            const bool e2 = (s2 == f2) == (a.jeff_sign > 0);
+            m |= (e0 && below(w0.x, thr_e)) ? 1u : 0u;
+            m |= (e2 && below(w0.y, thr_e)) ? 2u : 0u;
+        }
+        m |= (s0 == s1 && below(w0.z, thr_s)) ? 4u : 0u;
+        m |= (s0 == s2 && below(w0.w, thr_s)) ? 8u : 0u;
+        m |= (s0 == s3 && below(w1.x, thr_s)) ? 16u : 0u;
+        m |= (s1 == s2 && below(w1.y, thr_s)) ? 32u : 0u;
+        m |= (s1 == s3 && below(w1.z, thr_s)) ? 64u : 0u;
+        m |= (s2 == s3 && below(w1.w, thr_s)) ? 128u : 0u;
+        a.mask[c] = (uint8_t)m;
+        const uint32_t l4 = lut[m >> 2];
+        a.label[c] = (l4 & 3) * (uint32_t)N + c;
+        a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
+        a.label[2 * N + c] = ((l4 >> 4) & 3) * (uint32_t)N + c;
+        a.label[3 * N + c] = ((l4 >> 6) & 3) * (uint32_t)N + c;
+    }
+}
+
+// Root of x: follow parents until a self-loop.  label[x] <= x everywhere, so
+// the chain strictly decreases and ends.
+__device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
+{
+    uint32_t p = label[x];
+    while (p != x) {
+        x = p;
+        p = label[x];
+    }
+    return x;
+}
+
+// Lock-free union by minimum index (atomicMin on the larger root).  A failed
+// attempt means the larger root got a parent meanwhile; that parent is then
+// united with the smaller root, so no connection is lost.  The largest of
+// the two roots strictly decreases each round.
+__device__ void unite(uint32_t* label, uint32_t a, uint32_t b)
+{
+    a = find_root(label, a);
+    b = find_root(label, b);
+    while (a != b) {
+        if (a > b) {
+            const uint32_t tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const uint32_t old = atomicMin(label + b, a);
+        if (old == b) return;
+        b = find_root(label, old);
+        a = find_root(label, a);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
+{
+    const uint32_t L = a.L, N = a.N;
+    const double inv_L = 1.0 / (double)L;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < N; c += gridDim.x * kBlock) {
+        const uint32_t m = a.mask[c];
+        if (!(m & 3)) continue;
+        uint32_t x;
+        const uint32_t y = divmod(c, L, inv_L, x);
+        const uint32_t row = y * L;
+        if (m & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + row);
+        if (m & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : row + L));
+    }
+}
+
+// Flatten every label to its root (the cluster minimum) and shift sigma by
+// the cluster's r = pick(w0 of Philox(root, t, 0, SWF), q), NULL -> 0.
+__global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
+{
+    const uint32_t t = a.st->t_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->sw_done = 1;
+    const uint32_t N = a.N;
+    const int q = (int)a.q;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < N; c += gridDim.x * kBlock) {
+#pragma unroll
+        for (int arm = 0; arm < 4; ++arm) {
+            const uint32_t idx = arm * N + c;
+            const uint32_t r = find_root(a.label, idx);
+            a.label[idx] = r;
+            const uint32_t w = philox(r, t, 0u, kStreamSwf, a.key0, a.key1).x;
+            const int k = (w <= a.flip_lim) ? (int)((double)w * a.flip_invd) : 0;
+            int sv = a.sigma[idx] + k;
+            sv = sv >= q ? sv - q : sv;
+            a.sigma[idx] = (uint8_t)sv;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_state_init(DevState* st, int64_t* slots, double v_init, hipStream_t s)
+{
+    state_init_kernel<<<1, 64, 0, s>>>(st, slots, v_init);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s)
+{
+    sigma_init_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume(const VolArgs& a, hipStream_t s)
+{
+    volume_kernel<<<1, 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
+{
+    met_colour_kernel<<<grid_for(a.N / 2), kBlock, 0, s>>>(a, colour);
+    return hipGetLastError();
+}
+
+hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, hipStream_t s)
+{
+    recount_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a, out, spread, with_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_zero(DevObs* o, hipStream_t s)
+{
+    obs_zero_kernel<<<1, 64, 0, s>>>(o);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
+                            double Jsigma, double P, double vHB, hipStream_t s)
+{
+    obs_final_kernel<<<1, 64, 0, s>>>(o, st, tab, Nd, J, Jsigma, P, vHB);
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s)
+{
+    sw_bonds_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s)
+{
+    sw_union_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s)
+{
+    sw_flip_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace cvf

@@ -1,0 +1,227 @@
+"""ctypes binding of libcvf (include/cvf.h): argument marshalling only.
+
+Every function has the name of its C entry point and forwards to it; errors
+come back as ``CvfError``.  Device buffers are torch tensors on the GPU
+(their ``data_ptr()`` is passed), streams default to torch's current stream.
+The library must be built (``__graft_entry__.build()``); there is no
+fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcvf.so")
+
+CVF_OK, CVF_EINVAL, CVF_ENOMEM, CVF_EHIP, CVF_ESTATE = 0, -1, -2, -3, -4
+CVF_ALGO_METROPOLIS, CVF_ALGO_SW = 1, 2
+CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
+(CVF_K_VOLUME, CVF_K_MET_SWEEP, CVF_K_SW_BONDS, CVF_K_SW_UNION, CVF_K_SW_FLIP,
+ CVF_K_RECOUNT, CVF_K_COUNT) = range(7)
+
+EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
+           "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
+           "cvf_kernel_times", "cvf_destroy", "cvf_strerror"]
+
+
+class CvfError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {code} ({cvf_strerror(code)})")
+        self.code = code
+
+
+class cvf_params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("q", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("J", ctypes.c_double), ("Jsigma", ctypes.c_double), ("P", ctypes.c_double),
+                ("vHB", ctypes.c_double), ("v_init", ctypes.c_double), ("dv_max", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class cvf_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("n_hb_raw", ctypes.c_int64), ("n_hb", ctypes.c_int64),
+                ("n_coop", ctypes.c_int64), ("count", ctypes.c_int64 * 6),
+                ("met_attempted", ctypes.c_int64), ("met_accepted", ctypes.c_int64),
+                ("vol_attempted", ctypes.c_int64), ("vol_accepted", ctypes.c_int64),
+                ("v", ctypes.c_double), ("V", ctypes.c_double), ("H", ctypes.c_double),
+                ("M", ctypes.c_double), ("consistent", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["count"] = list(self.count)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libcvf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(cvf_params)
+        L.cvf_params_from_si.argtypes = [ctypes.c_double, ctypes.c_double, P]
+        L.cvf_workspace_bytes.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.cvf_init.argtypes = [P, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.cvf_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf_observables.argtypes = [vp, ctypes.POINTER(cvf_obs), vp]
+        L.cvf_labels.argtypes = [vp, vp, vp]
+        L.cvf_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]
+        L.cvf_timing_enable.argtypes = [vp, ctypes.c_int]
+        L.cvf_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.cvf_destroy.argtypes = [vp]
+        L.cvf_strerror.argtypes = [ctypes.c_int]
+        L.cvf_strerror.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "cvf_strerror":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, code):
+    if code != CVF_OK:
+        raise CvfError(fn, code)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _devptr(t, dtype_name, min_bytes):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous GPU tensors")
+    if str(t.dtype) != dtype_name:
+        raise ValueError(f"expected {dtype_name}, got {t.dtype}")
+    nbytes = t.numel() * t.element_size()
+    if nbytes < min_bytes:
+        raise ValueError(f"buffer of {nbytes} bytes, need {min_bytes}")
+    return ctypes.c_void_p(t.data_ptr()), nbytes
+
+
+def cvf_strerror(code: int) -> str:
+    return lib().cvf_strerror(code).decode()
+
+
+def cvf_params_from_si(T_kelvin: float, P_MPa: float, **override) -> cvf_params:
+    p = cvf_params()
+    _check("cvf_params_from_si", lib().cvf_params_from_si(T_kelvin, P_MPa, ctypes.byref(p)))
+    for k, v in override.items():
+        setattr(p, k, v)
+    return p
+
+
+def cvf_workspace_bytes(p: cvf_params, algo_mask: int) -> int:
+    n = ctypes.c_size_t()
+    _check("cvf_workspace_bytes", lib().cvf_workspace_bytes(ctypes.byref(p), algo_mask, ctypes.byref(n)))
+    return n.value
+
+
+def cvf_init(p: cvf_params, sigma, work, stream=None) -> ctypes.c_void_p:
+    N = p.L * p.L
+    sp, _ = _devptr(sigma, "torch.uint8", 4 * N)
+    wp, wbytes = _devptr(work, "torch.uint8", 1)
+    h = ctypes.c_void_p()
+    _check("cvf_init", lib().cvf_init(ctypes.byref(p), sp, wp, wbytes, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def cvf_metropolis_sweeps(st, nsweeps: int, stream=None):
+    _check("cvf_metropolis_sweeps", lib().cvf_metropolis_sweeps(st, nsweeps, _stream(stream)))
+
+
+def cvf_sw_steps(st, nsteps: int, stream=None):
+    _check("cvf_sw_steps", lib().cvf_sw_steps(st, nsteps, _stream(stream)))
+
+
+def cvf_observables(st, stream=None) -> dict:
+    o = cvf_obs()
+    _check("cvf_observables", lib().cvf_observables(st, ctypes.byref(o), _stream(stream)))
+    return o.as_dict()
+
+
+def cvf_labels(st, out, stream=None):
+    op, _ = _devptr(out, "torch.int32", 4)
+    _check("cvf_labels", lib().cvf_labels(st, op, _stream(stream)))
+    return out
+
+
+def cvf_tables(st):
+    import numpy as np
+    met = np.zeros((2, 3, 7), dtype=np.uint32)
+    sw = np.zeros(3, dtype=np.uint64)
+    _check("cvf_tables", lib().cvf_tables(st, met.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                          sw.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return met, sw
+
+
+def cvf_timing_enable(st, enable: bool):
+    _check("cvf_timing_enable", lib().cvf_timing_enable(st, 1 if enable else 0))
+
+
+def cvf_kernel_times(st, kind: int):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check("cvf_kernel_times", lib().cvf_kernel_times(st, kind, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def cvf_destroy(st):
+    _check("cvf_destroy", lib().cvf_destroy(st))
+
+
+class Chain:
+    """Convenience owner of one chain's device buffers (sigma, workspace) and
+    its library handle; every method forwards to the C entry point."""
+
+    def __init__(self, p: cvf_params, algo_mask: int = CVF_ALGO_METROPOLIS | CVF_ALGO_SW,
+                 stream=None, sigma=None):
+        import torch
+        self.p = cvf_params.from_buffer_copy(p)
+        self.N = p.L * p.L
+        self.sigma = sigma if sigma is not None else torch.empty(4 * self.N, dtype=torch.uint8, device="cuda")
+        self.work = torch.empty(cvf_workspace_bytes(self.p, algo_mask), dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        self.h = cvf_init(self.p, self.sigma, self.work, stream)
+
+    def metropolis(self, n):
+        cvf_metropolis_sweeps(self.h, n, self.stream)
+        return self
+
+    def sw(self, n):
+        cvf_sw_steps(self.h, n, self.stream)
+        return self
+
+    def obs(self):
+        return cvf_observables(self.h, self.stream)
+
+    def labels(self):
+        import torch
+        out = torch.empty(4 * self.N, dtype=torch.int32, device=self.sigma.device)
+        return cvf_labels(self.h, out, self.stream)
+
+    def tables(self):
+        return cvf_tables(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cvf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
