@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the CVF Monte Carlo hot path on one MI355X.
+
+Headline (the paper-scale Metropolis job): bond-variable updates per ns of
+checkerboard Metropolis sweeps (each with its volume move) on an L = 4096
+lattice (16.8 M molecules, 67.1 M uint8 bond indices) at 300 K and
+P in {0.1, 25, 50} MPa, one chain per pressure, lattices resident in HBM.
+Also reported: Swendsen-Wang steps/s on L = 1414 (~2 M molecules) at the
+same state points, the roofline of the dominant kernel, and the CPU oracle
+timed on a bounded sample of the same workload.
+
+One JSON line on stdout; progress on stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12     # full-rate 32-bit VALU lane-ops/s
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "met_colour_L4096_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2505_05919_amd", "csrc", "cvf_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_counters(launch_ms_unused=None):
+    """HBM bytes per colour launch from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, scaled by the same counters' reading of a plain copy of
+    known size; None when absent or taken on another kernel version."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    with open(COUNTERS_FILE) as f:
+        c = json.load(f)
+    if c.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    fetch = c["fetch_kib_per_dispatch"] * 1024.0 * c["fetch_scale"]
+    write = c["write_kib_per_dispatch"] * 1024.0 * c["write_scale"]
+    return fetch + write
+
+
+def make_chain(cvf, L, T, P, seed, algo_mask):
+    p = cvf.cvf_params_from_si(T, P, L=L, seed=seed)
+    return cvf.Chain(p, algo_mask)
+
+
+def timed(torch, fn, K):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        fn(i)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def instrumented(cvf, chains, fn, K, kinds):
+    for ch in chains:
+        cvf.cvf_timing_enable(ch.h, True)
+    for i in range(K):
+        fn(i)
+    out = {}
+    for k in kinds:
+        n_tot, ms_tot = 0, 0.0
+        for ch in chains:
+            n, ms = cvf.cvf_kernel_times(ch.h, k)
+            n_tot += n
+            ms_tot += n * ms
+        out[k] = (n_tot, ms_tot / n_tot if n_tot else 0.0)
+    for ch in chains:
+        cvf.cvf_timing_enable(ch.h, False)
+    return out
+
+
+def cpu_baseline(budget_s: float):
+    """The oracle as it stands (single thread), Metropolis on the headline
+    lattice, sweeps until the budget is used."""
+    import oracle
+    oracle.build(force=False)
+    op = oracle.params_from_si(300.0, 0.1, L=4096, seed=12)
+    ch = oracle.Chain(op)
+    n, t = 0, 0.0
+    while t < budget_s and n < 16:
+        t0 = time.perf_counter()
+        ch.metropolis(1)
+        t += time.perf_counter() - t0
+        n += 1
+    N = 4096 * 4096
+    return {"value": 4 * N * n / (t * 1e9), "unit": "bond-variable updates/ns", "cores": 1, "kind": "oracle",
+            "sample": f"oracle Metropolis L=4096 T=300K P=0.1MPa seed 12, {n} sweeps after init "
+                      f"({4 * N * n} updates, {t:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--skip-sw", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
+              "this build has no multi-GPU path; the workloads are single-lattice or independent jobs.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_05919_amd import cvf
+    from paper_2505_05919_amd.workloads import c3_jobs
+    cvf.lib()
+    torch.cuda.set_device(0)
+    K, W = args.steps, args.warmup
+
+    jobs = c3_jobs()
+    met_jobs = [j for j in jobs if j.algo == "met"]
+    sw_jobs = [j for j in jobs if j.algo == "sw"]
+
+    # ---------------- Metropolis L = 4096 (headline) ----------------
+    log(f"metropolis: {len(met_jobs)} chains L={met_jobs[0].L}, warmup {W}, steps {K}")
+    mch = [make_chain(cvf, j.L, j.T, j.P, j.seed, cvf.CVF_ALGO_METROPOLIS) for j in met_jobs]
+    N = met_jobs[0].L ** 2
+
+    def met_step(i):
+        mch[i % len(mch)].metropolis(1)
+
+    for i in range(W * len(mch)):
+        met_step(i)
+    t_met = timed(torch, met_step, K)
+    ms_per_step = t_met / K * 1e3
+    value = 4 * N * K / (t_met * 1e9)
+    log(f"metropolis: {ms_per_step:.4f} ms/sweep, {value:.1f} updates/ns")
+    ktimes = instrumented(cvf, mch, met_step, K, [cvf.CVF_K_MET_SWEEP, cvf.CVF_K_VOLUME])
+    n_launch, mean_ms = ktimes[cvf.CVF_K_MET_SWEEP]
+    upd_per_launch = 2 * N                      # one colour: N/2 cells x 4 arms
+    alg_bytes = 2 * upd_per_launch               # each uint8 read once + written once
+    achieved_gbs = alg_bytes / (mean_ms * 1e-3) / 1e9
+    traffic = traffic_from_counters()
+    roofline = {
+        "kernel": "met_colour_kernel (one checkerboard colour, L=4096)",
+        "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "launches_timed": n_launch, "mean_launch_ms": round(mean_ms, 5),
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "updates_per_launch": upd_per_launch,
+        "timing": "HIP events around every launch, separate instrumented pass of the same K steps",
+        "volume_kernel_mean_ms": round(ktimes[cvf.CVF_K_VOLUME][1], 5),
+    }
+    for ch in mch:
+        o = ch.obs()
+        assert o["consistent"] == 1, "incremental counters disagree with the recount"
+    for ch in mch:
+        ch.close()
+    del mch
+
+    # ---------------- Swendsen-Wang L = 1414 ----------------
+    sw = None
+    if not args.skip_sw:
+        log(f"sw: {len(sw_jobs)} chains L={sw_jobs[0].L}, warmup {W}, steps {K}")
+        sch = [make_chain(cvf, j.L, j.T, j.P, j.seed, cvf.CVF_ALGO_SW | cvf.CVF_ALGO_METROPOLIS) for j in sw_jobs]
+
+        def sw_step(i):
+            sch[i % len(sch)].sw(1)
+
+        for i in range(W * len(sch)):
+            sw_step(i)
+        t_sw = timed(torch, sw_step, K)
+        kinds = [cvf.CVF_K_VOLUME, cvf.CVF_K_SW_BONDS, cvf.CVF_K_SW_UNION, cvf.CVF_K_SW_FLIP, cvf.CVF_K_RECOUNT]
+        names = ["volume", "bonds", "union", "flip", "recount"]
+        kt = instrumented(cvf, sch, sw_step, K, kinds)
+        sw = {"L": sw_jobs[0].L, "steps_per_s": round(K / t_sw, 1), "ms_per_step": round(t_sw / K * 1e3, 4),
+              "kernel_mean_us": {nm: round(kt[k][1] * 1e3, 2) for k, nm in zip(kinds, names)}}
+        log(f"sw: {sw}")
+        for ch in sch:
+            assert ch.obs()["consistent"] == 1
+            ch.close()
+        del sch
+
+    if args.copy_calib:
+        # plain device copy of exactly 1 GiB: FETCH_SIZE / WRITE_SIZE calibration
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args.cpu_budget)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": "bond-variable updates/ns (L=4096 Metropolis); SW steps/s at 2M; p50/p99 job latency",
+        "value": round(value, 2), "unit": "bond-variable updates/ns",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "paper-scale single jobs: Metropolis L=4096 (16.8M molecules, 67.1M uint8 "
+                               "bond indices), T=300K, P in {0.1,25,50} MPa, one chain per P, a step = one "
+                               "sweep + one volume move of one chain (round robin); SW L=1414 likewise",
+                   "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
+        "sw": sw,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
