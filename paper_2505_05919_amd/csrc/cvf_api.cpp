@@ -11,6 +11,15 @@
 
 using namespace cvf;
 
+// Target number of wavefronts of a Metropolis colour launch.
+#ifndef CVF_MET_WAVES
+#define CVF_MET_WAVES 8192
+#endif
+// Use the dword (4-column) Metropolis kernel when L % 4 == 0.
+#ifndef CVF_MET_QUAD
+#define CVF_MET_QUAD 1
+#endif
+
 struct cvf_state {
     cvf_params p;
     uint8_t* sigma;
@@ -225,6 +234,22 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     a.jeff_sign = Jeff > 0.0 ? 1 : (Jeff < 0.0 ? -1 : 0);
     a.met_invd = 1.0 / (double)dm;
     a.flip_invd = 1.0 / (double)dq;
+    // Metropolis launch shape: lanes own column pairs (64 per wave), each wave
+    // walks `rows` rows; aim for CVF_MET_WAVES waves in the grid.
+    {
+        a.quad = (a.L % 4 == 0) ? CVF_MET_QUAD : 0;
+        const uint32_t per_lane = a.quad ? 4 : 2;           // columns owned by a lane
+        const uint32_t groups = (a.L / per_lane + 63) / 64;
+        const uint32_t target = CVF_MET_WAVES;
+        const uint32_t waves_per_group = groups >= target ? 1 : target / groups;
+        uint32_t rows = (a.L + waves_per_group - 1) / waves_per_group;
+        rows = (rows + 1) & ~1u;
+        if (rows < 2) rows = 2;
+        if (rows > 32) rows = 32;
+        const uint32_t segs = (a.L + rows - 1) / rows;
+        a.rows = rows;
+        a.row_blocks = (segs + 3) / 4;
+    }
 
     VolArgs& v = st->va;
     v.st = st->dst;
@@ -243,7 +268,7 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     v.do_volume = (p->flags & CVF_NO_VOLUME_MOVE) ? 0 : 1;
 
     hipError_t e = hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, p->v_init, s);
+    if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, st->dtab, p->v_init, s);
     if (e == hipSuccess && !(p->flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(a, s);
     if (e == hipSuccess) e = launch_recount(a, st->slots, kSlots, 0, s);
     if (e != hipSuccess) {

@@ -17,7 +17,7 @@ constexpr uint32_t kStreamSwf = 4;    // Swendsen-Wang cluster shift
 
 // Per-workgroup partial sums are spread over this many int64 slots so that
 // same-address atomics do not serialise; the volume kernel folds them.
-constexpr int kSlots = 64;
+constexpr int kSlots = 256;
 
 // Mutable per-chain scalars, at offset 0 of the workspace.
 struct DevState {
@@ -26,6 +26,7 @@ struct DevState {
     int64_t n_coop;
     int64_t met_att, met_acc, vol_att, vol_acc;
     double v;                // v_iso / v0
+    double u;                // u_LJ(v), cached: the volume move needs u(v) and u(v')
     uint32_t t_cur;          // step being executed (Philox counter word 1)
     int32_t theta;           // 1 liquid (v < 2), 0 gas
     int32_t sw_done;         // a Swendsen-Wang step has produced labels
@@ -49,9 +50,9 @@ struct DevObs {
 // Workspace layout (byte offsets, all 256-aligned).
 constexpr size_t kOffState = 0;
 constexpr size_t kOffSlots = 256;
-constexpr size_t kOffTables = kOffSlots + 3 * kSlots * sizeof(int64_t);   // 1792
-constexpr size_t kOffObs = kOffTables + 768;                                // 2560
-constexpr size_t kBaseBytes = kOffObs + 512;                                // 3072
+constexpr size_t kOffTables = kOffSlots + 3 * kSlots * sizeof(int64_t);   // 6400
+constexpr size_t kOffObs = kOffTables + 768;                                // 7168
+constexpr size_t kBaseBytes = kOffObs + 512;                                // 7680
 
 static_assert(sizeof(DevState) <= 256, "DevState");
 static_assert(sizeof(DevTables) <= 768, "DevTables");
@@ -73,6 +74,9 @@ struct LatticeArgs {
     int32_t jeff_sign;       // sign of J_eff = J - P v_HB
     double met_invd;         // 1 / floor(2^32/(q-1))
     double flip_invd;        // 1 / floor(2^32/q)
+    uint32_t rows;           // Metropolis: rows per wavefront (even, <= 32)
+    uint32_t row_blocks;     // Metropolis: grid.y
+    uint32_t quad;           // Metropolis: 1 = dword (4-column) lanes, needs L % 4 == 0
 };
 
 struct VolArgs {
@@ -89,7 +93,7 @@ struct VolArgs {
 enum VolMode { kVolMet = 0, kVolSw = 1, kVolFold = 2 };
 
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
-hipError_t launch_state_init(DevState* st, int64_t* slots, double v_init, hipStream_t s);
+hipError_t launch_state_init(DevState* st, int64_t* slots, const DevTables* tab, double v_init, hipStream_t s);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
