@@ -24,9 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12     # full-rate 32-bit VALU lane-ops/s
+# full-rate 32-bit VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic integer ops per bond update: half a Philox4x32-10 block (10 rounds x
+# (2 single-instruction 32x32->64 products + 4 XORs) / 2 = 30) + the decision (14)
+ALU_OPS_PER_UPDATE = 44
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "met_colour_L4096_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2505_05919_amd", "csrc", "cvf_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "met_sweep.h")]
 
 
 def log(*a):
@@ -34,8 +38,12 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the Metropolis colour kernel is built from."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_counters(launch_ms_unused=None):
@@ -104,6 +112,67 @@ def cpu_baseline(budget_s: float):
                       f"({4 * N * n} updates, {t:.1f} s, one thread)"}
 
 
+def bench_batched(torch, cvf, sweeps, alone_sweeps):
+    """256 independent replicas of uneven L (log-uniform 64..512) on a 16x16
+    (T, P) grid: one batched launch per colour phase, 100-sweep blocks replayed
+    from a hipGraph, launch shape from the autotuner -- against the same jobs
+    run one at a time with plain launches; per-replica sigma digests must be
+    identical at equal sweep counts."""
+    import hashlib
+    from paper_2505_05919_amd.workloads import c4_jobs
+    jobs = c4_jobs()
+
+    def chains():
+        return [make_chain(cvf, j.L, j.T, j.P, j.seed, cvf.CVF_ALGO_METROPOLIS) for j in jobs]
+
+    def digests(chs):
+        return [hashlib.sha256(c.sigma.cpu().numpy().tobytes()).hexdigest() for c in chs]
+
+    upd_per_sweep = sum(4 * j.L * j.L for j in jobs)
+    tune = chains()
+    b = cvf.Batch(tune)
+    rows = b.autotune(3)
+    b.close()
+    for c in tune:
+        c.close()
+    chs = chains()
+    b = cvf.Batch(chs)
+    b.set_rows(rows)
+    block = 100 if sweeps % 100 == 0 else 0
+    b.metropolis(block if block else 1, graph_block=block)      # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.metropolis(sweeps, graph_block=block)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    # identity check at alone_sweeps: fresh batch vs fresh single chains
+    chk = chains()
+    bb = cvf.Batch(chk)
+    bb.set_rows(rows)
+    bb.metropolis(alone_sweeps, graph_block=0)
+    d_batch = digests(chk)
+    bb.close()
+    for c in chk:
+        c.close()
+    alone = chains()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in alone:
+        c.metropolis(alone_sweeps)
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    d_alone = digests(alone)
+    for c in alone + chs:
+        c.close()
+    v_batch = upd_per_sweep * sweeps / t_batch / 1e9
+    v_alone = upd_per_sweep * alone_sweeps / t_alone / 1e9
+    return {"replicas": len(jobs), "sweeps": sweeps, "graph_block": block, "rows": rows,
+            "updates_per_ns": round(v_batch, 1), "ms": round(t_batch * 1e3, 2),
+            "one_at_a_time_updates_per_ns": round(v_alone, 2), "speedup": round(v_batch / v_alone, 1),
+            "identical_digests": d_batch == d_alone, "digests_compared_at_sweeps": alone_sweeps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +183,10 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--skip-sw", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--batch-sweeps", type=int, default=1000)
+    ap.add_argument("--alone-sweeps", type=int, default=100,
+                    help="sweeps per replica for the one-at-a-time comparison (digests compared at this count)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -152,15 +225,23 @@ def main():
     n_launch, mean_ms = ktimes[cvf.CVF_K_MET_SWEEP]
     upd_per_launch = 2 * N                      # one colour: N/2 cells x 4 arms
     alg_bytes = 2 * upd_per_launch               # each uint8 read once + written once
-    achieved_gbs = alg_bytes / (mean_ms * 1e-3) / 1e9
+    alg_ops = ALU_OPS_PER_UPDATE * upd_per_launch
+    secs = mean_ms * 1e-3
+    achieved_tops = alg_ops / secs / 1e12
+    achieved_gbs = alg_bytes / secs / 1e9
     traffic = traffic_from_counters()
     roofline = {
-        "kernel": "met_colour_kernel (one checkerboard colour, L=4096)",
-        "bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "kernel": "met_sweep4_kernel (one checkerboard colour, L=4096)",
+        "bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "Tops/s (32-bit integer VALU lane-ops)",
+        "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
         "traffic": traffic,
+        "alu_ops_per_update": ALU_OPS_PER_UPDATE,
+        "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "traffic_gbs": round(traffic / secs / 1e9, 1) if traffic else None},
         "launches_timed": n_launch, "mean_launch_ms": round(mean_ms, 5),
-        "algorithmic_bytes_per_launch": alg_bytes,
+        "algorithmic_bytes_per_launch": alg_bytes, "algorithmic_ops_per_launch": alg_ops,
         "updates_per_launch": upd_per_launch,
         "timing": "HIP events around every launch, separate instrumented pass of the same K steps",
         "volume_kernel_mean_ms": round(ktimes[cvf.CVF_K_VOLUME][1], 5),
@@ -195,6 +276,11 @@ def main():
             ch.close()
         del sch
 
+    batched = None
+    if not args.skip_batch:
+        batched = bench_batched(torch, cvf, args.batch_sweeps, args.alone_sweeps)
+        log(f"batched: {batched}")
+
     if args.copy_calib:
         # plain device copy of exactly 1 GiB: FETCH_SIZE / WRITE_SIZE calibration
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -221,6 +307,7 @@ def main():
                                "sweep + one volume move of one chain (round robin); SW L=1414 likewise",
                    "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
         "sw": sw,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -169,6 +169,44 @@ int cvf_kernel_times(cvf_state *st, int kind, int64_t *launches, double *mean_ms
 /* Release the host state (device memory stays with the caller). */
 int cvf_destroy(cvf_state *st);
 
+/* ---------------------------------------------------------------------------
+ * Batched execution: many independent chains advanced together, one launch
+ * per colour phase for all of them (plus one volume launch with a wavefront
+ * per chain).  Every chain computes exactly what cvf_metropolis_sweeps
+ * computes for it alone (same Philox keying, same update order), so results
+ * are identical alone and in the batch.
+ * ------------------------------------------------------------------------- */
+typedef struct cvf_batch cvf_batch;
+
+/* Device bytes for the descriptor table of `count` chains. */
+int cvf_batch_desc_bytes(int32_t count, size_t *bytes);
+
+/* Group `count` existing chains (created by cvf_init, all with the same q;
+ * each keeps its own sigma and workspace).  d_desc: caller-owned device
+ * memory of cvf_batch_desc_bytes(count) bytes, 256-byte aligned.  The
+ * chains must outlive the batch; the batch holds no device memory of its own
+ * besides a private capture stream for graphs.  Asynchronous on stream. */
+int cvf_batch_create(cvf_state *const *chains, int32_t count, void *d_desc, size_t desc_bytes,
+                     void *stream, cvf_batch **out);
+
+/* Launch shape: every wavefront walks `rows` rows (even, 2..32); 0 restores
+ * each chain's own default.  Invalidates captured graphs.  Asynchronous. */
+int cvf_batch_set_rows(cvf_batch *b, int32_t rows, void *stream);
+
+/* nsweeps Metropolis MC steps of every chain.  graph_block > 0: the sweeps
+ * run as replays of one hipGraph holding graph_block sweeps (captured once,
+ * on first use), the remainder as plain launches; 0: plain launches.
+ * Asynchronous. */
+int cvf_batch_metropolis_sweeps(cvf_batch *b, int64_t nsweeps, int32_t graph_block, void *stream);
+
+/* Autotuner: times `sweeps` sweeps for each candidate rows value (2, 4, 8,
+ * 16, 32) with HIP events and keeps the fastest; *rows_out receives it.
+ * The timed sweeps are real: every chain advances by 5 * sweeps steps.
+ * Synchronises stream. */
+int cvf_batch_autotune(cvf_batch *b, int32_t sweeps, void *stream, int32_t *rows_out);
+
+int cvf_batch_destroy(cvf_batch *b);
+
 /* Static description of an error code. */
 const char *cvf_strerror(int code);
 

@@ -383,6 +383,227 @@ int cvf_destroy(cvf_state* st)
     return CVF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct cvf_batch {
+    std::vector<cvf_state*> chains;
+    std::vector<BatchEntry> host;     // descriptor source (kept alive for async copies)
+    std::vector<uint32_t> start;      // prefix sums of workgroups, count + 1
+    BatchEntry* d_ent;
+    uint32_t* d_start;
+    uint32_t total_blocks;
+    int q;
+    int32_t rows;                     // 0 = per-chain default
+    hipStream_t capture;              // private stream for graph capture
+    hipGraphExec_t exec;
+    int32_t exec_block;               // sweeps held by exec (0 = none)
+};
+
+namespace {
+
+size_t batch_layout(int32_t count, size_t* off_start)
+{
+    const size_t ent = align256((size_t)count * sizeof(BatchEntry));
+    *off_start = ent;
+    return ent + align256(((size_t)count + 1) * sizeof(uint32_t));
+}
+
+uint32_t met_rows_for(uint32_t L, uint32_t quad, uint32_t target_waves)
+{
+    const uint32_t per_lane = quad ? 4 : 2;
+    const uint32_t groups = (L / per_lane + 63) / 64;
+    const uint32_t waves_per_group = groups >= target_waves ? 1 : target_waves / groups;
+    uint32_t rows = (L + waves_per_group - 1) / waves_per_group;
+    rows = (rows + 1) & ~1u;
+    if (rows < 2) rows = 2;
+    if (rows > 32) rows = 32;
+    return rows;
+}
+
+void drop_graph(cvf_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->exec_block = 0;
+}
+
+int batch_upload(cvf_batch* b, hipStream_t s)
+{
+    const uint32_t count = (uint32_t)b->chains.size();
+    b->host.resize(count);
+    b->start.assign(count + 1, 0);
+    uint32_t total = 0;
+    for (uint32_t c = 0; c < count; ++c) {
+        const cvf_state* st = b->chains[c];
+        BatchEntry& e = b->host[c];
+        memset(&e, 0, sizeof(e));
+        e.la = st->la;
+        if (b->rows > 0) {
+            const uint32_t segs = (e.la.L + b->rows - 1) / (uint32_t)b->rows;
+            e.la.rows = (uint32_t)b->rows;
+            e.la.row_blocks = (segs + 3) / 4;
+        }
+        e.va = st->va;
+        e.va.mode = kVolMet;
+        e.va.met_att_add = 4 * (int64_t)st->N;
+        const uint32_t per_lane = e.la.quad ? 4 : 2;
+        e.groups_x = (e.la.L / per_lane + 63) / 64;
+        e.blocks = e.groups_x * e.la.row_blocks;
+        b->start[c] = total;
+        total += e.blocks;
+    }
+    b->start[count] = total;
+    b->total_blocks = total;
+    hipError_t e = hipMemcpyAsync(b->d_ent, b->host.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_start, b->start.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    // the host vectors must stay unchanged until the copies are done
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_status(e);
+}
+
+hipError_t batch_sweep(cvf_batch* b, hipStream_t s)
+{
+    const uint32_t count = (uint32_t)b->chains.size();
+    hipError_t e = launch_volume_batch(b->d_ent, count, s);
+    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 0, s);
+    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 1, s);
+    return e;
+}
+
+int batch_capture(cvf_batch* b, int32_t block)
+{
+    drop_graph(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    for (int32_t i = 0; e == hipSuccess && i < block; ++i) e = batch_sweep(b, b->capture);
+    hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->exec = nullptr;
+        return CVF_EHIP;
+    }
+    b->exec_block = block;
+    return CVF_OK;
+}
+
+}  // namespace
+
+int cvf_batch_desc_bytes(int32_t count, size_t* bytes)
+{
+    if (!bytes || count <= 0) return CVF_EINVAL;
+    size_t off;
+    *bytes = batch_layout(count, &off);
+    return CVF_OK;
+}
+
+int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size_t desc_bytes, void* stream,
+                     cvf_batch** out)
+{
+    if (!chains || count <= 0 || !d_desc || !out) return CVF_EINVAL;
+    if (((uintptr_t)d_desc & 255) != 0) return CVF_EINVAL;
+    size_t off_start;
+    if (desc_bytes < batch_layout(count, &off_start)) return CVF_ENOMEM;
+    for (int32_t c = 0; c < count; ++c)
+        if (!chains[c] || chains[c]->p.q != chains[0]->p.q) return CVF_EINVAL;
+    cvf_batch* b = new (std::nothrow) cvf_batch();
+    if (!b) return CVF_EINVAL;
+    b->chains.assign(chains, chains + count);
+    b->d_ent = (BatchEntry*)d_desc;
+    b->d_start = (uint32_t*)((char*)d_desc + off_start);
+    b->q = chains[0]->p.q;
+    b->rows = 0;
+    b->exec = nullptr;
+    b->exec_block = 0;
+    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return CVF_EHIP;
+    }
+    int rc = batch_upload(b, (hipStream_t)stream);
+    if (rc) {
+        (void)hipStreamDestroy(b->capture);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return CVF_OK;
+}
+
+int cvf_batch_set_rows(cvf_batch* b, int32_t rows, void* stream)
+{
+    if (!b || rows < 0 || rows > 32 || (rows & 1)) return CVF_EINVAL;
+    drop_graph(b);
+    b->rows = rows;
+    return batch_upload(b, (hipStream_t)stream);
+}
+
+int cvf_batch_metropolis_sweeps(cvf_batch* b, int64_t nsweeps, int32_t graph_block, void* stream)
+{
+    if (!b || nsweeps < 0 || graph_block < 0) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t done = 0;
+    if (graph_block > 0 && nsweeps >= graph_block) {
+        if (b->exec_block != graph_block) {
+            int rc = batch_capture(b, graph_block);
+            if (rc) return rc;
+        }
+        for (; done + graph_block <= nsweeps; done += graph_block)
+            if (hipGraphLaunch(b->exec, s) != hipSuccess) return CVF_EHIP;
+    }
+    for (; done < nsweeps; ++done)
+        if (batch_sweep(b, s) != hipSuccess) return CVF_EHIP;
+    return CVF_OK;
+}
+
+int cvf_batch_autotune(cvf_batch* b, int32_t sweeps, void* stream, int32_t* rows_out)
+{
+    if (!b || sweeps <= 0 || !rows_out) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t cand[5] = {2, 4, 8, 16, 32};
+    float best = 0.f;
+    int32_t best_rows = 0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return CVF_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CVF_EHIP;
+    }
+    int rc = CVF_OK;
+    for (int i = 0; i < 5 && rc == CVF_OK; ++i) {
+        rc = cvf_batch_set_rows(b, cand[i], stream);
+        if (rc) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = CVF_EHIP; break; }
+        for (int32_t k = 0; k < sweeps && rc == CVF_OK; ++k)
+            if (batch_sweep(b, s) != hipSuccess) rc = CVF_EHIP;
+        float ms = 0.f;
+        if (rc == CVF_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = CVF_EHIP;
+        if (rc == CVF_OK && (best_rows == 0 || ms < best)) {
+            best = ms;
+            best_rows = cand[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = cvf_batch_set_rows(b, best_rows, stream);
+    if (rc == CVF_OK) *rows_out = best_rows;
+    return rc;
+}
+
+int cvf_batch_destroy(cvf_batch* b)
+{
+    if (!b) return CVF_EINVAL;
+    drop_graph(b);
+    (void)hipStreamDestroy(b->capture);
+    delete b;
+    return CVF_OK;
+}
+
 const char* cvf_strerror(int code)
 {
     switch (code) {

@@ -92,6 +92,16 @@ struct VolArgs {
 
 enum VolMode { kVolMet = 0, kVolSw = 1, kVolFold = 2 };
 
+// One chain of a batch: its launch arguments, its own launch shape
+// (groups_x workgroups per row block) and its workgroup count.
+struct BatchEntry {
+    LatticeArgs la;
+    VolArgs va;
+    uint32_t groups_x;
+    uint32_t blocks;
+    uint32_t pad_[2];
+};
+
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
 hipError_t launch_state_init(DevState* st, int64_t* slots, const DevTables* tab, double v_init, hipStream_t s);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
@@ -104,5 +114,10 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
 hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
+// Batched Metropolis: `ent` / `start` are device arrays (count entries,
+// count+1 prefix sums of workgroups); all chains share q.
+hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
+                            int q, int colour, hipStream_t s);
+hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, hipStream_t s);
 
 }  // namespace cvf

@@ -22,7 +22,8 @@ CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
 
 EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
-           "cvf_kernel_times", "cvf_destroy", "cvf_strerror"]
+           "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_batch_desc_bytes", "cvf_batch_create",
+           "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_autotune", "cvf_batch_destroy"]
 
 
 class CvfError(RuntimeError):
@@ -78,6 +79,13 @@ def lib():
         L.cvf_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
         L.cvf_destroy.argtypes = [vp]
+        L.cvf_batch_desc_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.cvf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.c_size_t, vp,
+                                       ctypes.POINTER(vp)]
+        L.cvf_batch_set_rows.argtypes = [vp, ctypes.c_int32, vp]
+        L.cvf_batch_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp]
+        L.cvf_batch_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
+        L.cvf_batch_destroy.argtypes = [vp]
         L.cvf_strerror.argtypes = [ctypes.c_int]
         L.cvf_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -180,6 +188,71 @@ def cvf_kernel_times(st, kind: int):
 
 def cvf_destroy(st):
     _check("cvf_destroy", lib().cvf_destroy(st))
+
+
+def cvf_batch_desc_bytes(count: int) -> int:
+    n = ctypes.c_size_t()
+    _check("cvf_batch_desc_bytes", lib().cvf_batch_desc_bytes(count, ctypes.byref(n)))
+    return n.value
+
+
+def cvf_batch_create(handles, desc, stream=None) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    dp, nbytes = _devptr(desc, "torch.uint8", 1)
+    b = ctypes.c_void_p()
+    _check("cvf_batch_create", lib().cvf_batch_create(arr, len(handles), dp, nbytes, _stream(stream), ctypes.byref(b)))
+    return b
+
+
+def cvf_batch_set_rows(b, rows: int, stream=None):
+    _check("cvf_batch_set_rows", lib().cvf_batch_set_rows(b, rows, _stream(stream)))
+
+
+def cvf_batch_metropolis_sweeps(b, nsweeps: int, graph_block: int = 0, stream=None):
+    _check("cvf_batch_metropolis_sweeps", lib().cvf_batch_metropolis_sweeps(b, nsweeps, graph_block, _stream(stream)))
+
+
+def cvf_batch_autotune(b, sweeps: int, stream=None) -> int:
+    r = ctypes.c_int32()
+    _check("cvf_batch_autotune", lib().cvf_batch_autotune(b, sweeps, _stream(stream), ctypes.byref(r)))
+    return r.value
+
+
+def cvf_batch_destroy(b):
+    _check("cvf_batch_destroy", lib().cvf_batch_destroy(b))
+
+
+class Batch:
+    """Owner of a batch's descriptor buffer; the chains stay owned by their
+    Chain objects (which must outlive the batch)."""
+
+    def __init__(self, chains, stream=None):
+        import torch
+        self.chains = list(chains)
+        self.desc = torch.empty(cvf_batch_desc_bytes(len(self.chains)), dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        self.h = cvf_batch_create([c.h for c in self.chains], self.desc, stream)
+
+    def metropolis(self, n, graph_block=0):
+        cvf_batch_metropolis_sweeps(self.h, n, graph_block, self.stream)
+        return self
+
+    def set_rows(self, rows):
+        cvf_batch_set_rows(self.h, rows, self.stream)
+
+    def autotune(self, sweeps=3):
+        return cvf_batch_autotune(self.h, sweeps, self.stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            cvf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Chain:

@@ -1,0 +1,127 @@
+"""Batched execution (many chains, one launch per colour phase): every chain
+must follow exactly the trajectory it follows alone, and small ones the
+oracle's, whatever the launch shape (rows per wavefront) or graph replay."""
+import hashlib
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cvf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05919_amd import cvf as mod
+    mod.lib()
+    return mod
+
+
+def params(cvf, L, T, P, seed, **kw):
+    return cvf.cvf_params_from_si(T, P, L=L, seed=seed, **kw)
+
+
+def digest(ch):
+    return hashlib.sha256(ch.sigma.cpu().numpy().tobytes()).hexdigest()
+
+
+def mixed_jobs(n, seed=3):
+    rng = np.random.default_rng(seed)
+    Ls = [int(2 * round(np.exp(rng.uniform(np.log(6), np.log(300))) / 2)) for _ in range(n)]
+    Ls[:4] = [2, 4, 66, 128]                      # degenerate, quad, byte-lane and quad layouts
+    return [(L, 270.0 + 60.0 * rng.random(), 50.0 * rng.random(), 500 + k) for k, L in enumerate(Ls)]
+
+
+@pytest.mark.parametrize("rows,graph", [(0, 0), (2, 0), (8, 0), (32, 5), (4, 3)])
+def test_batch_equals_alone(cvf, rows, graph):
+    jobs = mixed_jobs(24)
+    say(f"case batch rows={rows} graph={graph} Ls={[j[0] for j in jobs]}")
+    alone = []
+    for L, T, P, s in jobs:
+        ch = cvf.Chain(params(cvf, L, T, P, s), cvf.CVF_ALGO_METROPOLIS)
+        ch.metropolis(7)
+        alone.append((digest(ch), ch.obs()))
+        ch.close()
+    chains = [cvf.Chain(params(cvf, L, T, P, s), cvf.CVF_ALGO_METROPOLIS) for L, T, P, s in jobs]
+    b = cvf.Batch(chains)
+    if rows:
+        b.set_rows(rows)
+    b.metropolis(7, graph_block=graph)
+    for k, ch in enumerate(chains):
+        o = ch.obs()
+        assert digest(ch) == alone[k][0], (k, jobs[k])
+        assert o == alone[k][1], (k, jobs[k])
+        assert o["consistent"] == 1
+    b.close()
+    for ch in chains:
+        ch.close()
+
+
+def test_batch_vs_oracle_and_mixed_calls(cvf, oracle_mod):
+    """Batched sweeps interleaved with single-chain Metropolis and SW calls
+    on the same chains, against the oracle doing the same sequence."""
+    jobs = [(2, 300.0, 0.1, 11), (6, 280.0, 10.0, 12), (40, 320.0, 40.0, 13), (64, 300.0, 0.1, 14)]
+    chains, orcs = [], []
+    for L, T, P, s in jobs:
+        op = oracle_mod.params_from_si(T, P, L=L, seed=s)
+        p = cvf.cvf_params()
+        for k, v in op.as_dict().items():
+            setattr(p, k, v)
+        chains.append(cvf.Chain(p))
+        orcs.append(oracle_mod.Chain(op))
+    b = cvf.Batch(chains)
+    b.metropolis(3)
+    chains[1].sw(2)
+    chains[2].metropolis(1)
+    b.metropolis(4, graph_block=2)
+    for o in orcs:
+        o.metropolis(3)
+    orcs[1].sw(2)
+    orcs[2].metropolis(1)
+    for o in orcs:
+        o.metropolis(4)
+    for ch, oc in zip(chains, orcs):
+        assert np.array_equal(ch.sigma.cpu().numpy(), oc.sigma())
+        og, oo = ch.obs(), oc.obs()
+        for k in ("step", "n_hb_raw", "n_coop", "met_accepted", "vol_accepted", "count"):
+            assert og[k] == oo[k], k
+        assert og["v"] == pytest.approx(oo["v"], rel=1e-12)
+    b.close()
+    for ch in chains:
+        ch.close()
+
+
+def test_batch_autotune_and_graph_replays(cvf):
+    jobs = mixed_jobs(16, seed=9)
+    chains = [cvf.Chain(params(cvf, L, T, P, s), cvf.CVF_ALGO_METROPOLIS) for L, T, P, s in jobs]
+    b = cvf.Batch(chains)
+    rows = b.autotune(2)
+    assert rows in (2, 4, 8, 16, 32)
+    b.metropolis(9, graph_block=4)        # two replays + one plain sweep
+    b.metropolis(8, graph_block=4)        # two more replays of the same graph
+    got = [digest(ch) for ch in chains]
+    b.close()
+    for ch in chains:
+        ch.close()
+    for k, (L, T, P, s) in enumerate(jobs):
+        ch = cvf.Chain(params(cvf, L, T, P, s), cvf.CVF_ALGO_METROPOLIS)
+        ch.metropolis(5 * 2 + 17)
+        assert digest(ch) == got[k], k
+        ch.close()
+
+
+def test_batch_rejects_mixed_q(cvf):
+    a = cvf.Chain(params(cvf, 8, 300.0, 0.1, 1), cvf.CVF_ALGO_METROPOLIS)
+    b = cvf.Chain(params(cvf, 8, 300.0, 0.1, 2, q=4), cvf.CVF_ALGO_METROPOLIS)
+    with pytest.raises(cvf.CvfError):
+        cvf.Batch([a, b])
+    a.close()
+    b.close()
