@@ -15,6 +15,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import sys
@@ -173,6 +175,45 @@ def bench_batched(torch, cvf, sweeps, alone_sweeps):
             "identical_digests": d_batch == d_alone, "digests_compared_at_sweeps": alone_sweeps}
 
 
+def bench_served(torch, n_jobs):
+    """The served stream: Poisson arrivals at 200 jobs/s, L log-uniform 32..2048,
+    T ~ U(270, 330) K, P ~ U(0, 50) MPa, nsteps ~ U[100, 10^4], 80 % Metropolis /
+    20 % SW, admitted by HBM footprint, lattices resident; p50/p99 latency next
+    to throughput, against a one-job-at-a-time FCFS server with plain launches
+    on the same trace (service times measured job by job)."""
+    from paper_2505_05919_amd import serve
+    from paper_2505_05919_amd.workloads import c5_stream
+    jobs = c5_stream(n_jobs=n_jobs)
+    srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True)
+    recs = srv.run(jobs, realtime=True)
+    s = serve.summarize(recs)
+    by_seed = {r.job.seed: r for r in recs}
+    service, same = [], True
+    for j in jobs:
+        o, dg, dt = serve.run_alone(j)
+        service.append(dt)
+        r = by_seed[j.seed]
+        same = same and r.digest == dg and r.obs == o
+    lat = serve.fcfs_latencies(jobs, service)
+    span_alone = max(max(j.arrival for j in jobs), 0.0)
+    done = 0.0
+    for j, t in zip(jobs, service):
+        done = max(done, j.arrival) + t
+    upd = sum(4 * j.L ** 2 * j.nsteps for j in jobs if j.algo == "met")
+    offered = upd / max(j.arrival for j in jobs) / 1e9
+    return {"jobs": n_jobs, "rate_per_s": 200.0, "quantum": srv.quantum,
+            "p50_ms": round(s["p50_s"] * 1e3, 1), "p99_ms": round(s["p99_s"] * 1e3, 1),
+            "queue_p50_ms": round(s["queue_p50_s"] * 1e3, 1), "queue_p99_ms": round(s["queue_p99_s"] * 1e3, 1),
+            "makespan_s": round(s["makespan_s"], 3), "met_updates_per_ns": round(s["met_updates_per_ns"], 1),
+            "offered_met_updates_per_ns": round(offered, 1),
+            "peak_resident_jobs": srv.peak_resident_jobs, "peak_resident_MB": round(srv.peak_resident_bytes / 2**20, 1),
+            "one_at_a_time": {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+                              "makespan_s": round(done - min(j.arrival for j in jobs), 3),
+                              "met_updates_per_ns": round(upd / (done - min(j.arrival for j in jobs)) / 1e9, 1)},
+            "identical_to_alone": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +226,8 @@ def main():
     ap.add_argument("--skip-sw", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-sweeps", type=int, default=1000)
+    ap.add_argument("--serve-jobs", type=int, default=120,
+                    help="jobs of the served Poisson stream (0 = skip)")
     ap.add_argument("--alone-sweeps", type=int, default=100,
                     help="sweeps per replica for the one-at-a-time comparison (digests compared at this count)")
     args = ap.parse_args()
@@ -281,6 +324,11 @@ def main():
         batched = bench_batched(torch, cvf, args.batch_sweeps, args.alone_sweeps)
         log(f"batched: {batched}")
 
+    served = None
+    if args.serve_jobs > 0:
+        served = bench_served(torch, args.serve_jobs)
+        log(f"served: {served}")
+
     if args.copy_calib:
         # plain device copy of exactly 1 GiB: FETCH_SIZE / WRITE_SIZE calibration
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -308,6 +356,7 @@ def main():
                    "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
         "sw": sw,
         "batched": batched,
+        "served": served,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

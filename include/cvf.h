@@ -199,6 +199,11 @@ int cvf_batch_set_rows(cvf_batch *b, int32_t rows, void *stream);
  * Asynchronous. */
 int cvf_batch_metropolis_sweeps(cvf_batch *b, int64_t nsweeps, int32_t graph_block, void *stream);
 
+/* nsteps Swendsen-Wang MC steps of every chain (each chain as in
+ * cvf_sw_steps), one launch per stage for all chains.  CVF_ENOMEM unless
+ * every chain has the Swendsen-Wang workspace.  Asynchronous. */
+int cvf_batch_sw_steps(cvf_batch *b, int64_t nsteps, void *stream);
+
 /* Autotuner: times `sweeps` sweeps for each candidate rows value (2, 4, 8,
  * 16, 32) with HIP events and keeps the fastest; *rows_out receives it.
  * The timed sweeps are real: every chain advances by 5 * sweeps steps.

@@ -118,6 +118,10 @@ hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
 // count+1 prefix sums of workgroups); all chains share q.
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                             int q, int colour, hipStream_t s);
-hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, hipStream_t s);
+hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s);
+// Batched Swendsen-Wang stage (0 bonds, 1 union, 2 flip, 3 recount); swstart:
+// count+1 prefix sums of ceil(N/256) workgroups per chain.
+hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint32_t count, uint32_t total_blocks,
+                           int stage, hipStream_t s);
 
 }  // namespace cvf

@@ -212,39 +212,7 @@ __global__ __launch_bounds__(64) void volume_kernel(VolArgs a)
 
 #include "met_sweep.h"
 
-// ---------------------------------------------------------------------------
-// Full recount of N_HB_raw, N_sigma (and optionally N_q').
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts)
-{
-    const uint32_t L = a.L;
-    const size_t N = a.N;
-    const double inv_L = 1.0 / (double)L;
-    const uint8_t* __restrict__ s = a.sigma;
-    int hb = 0, co = 0;
-    int cnt[6] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
-        uint32_t x;
-        const uint32_t y = divmod(c, L, inv_L, x);
-        const uint32_t row = y * L;
-        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-        const uint32_t rp = (y + 1 == L) ? 0 : row + L;
-        const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
-        hb += (s0 == s[N + xp + row]) + (s2 == s[3 * N + x + rp]);
-        co += (s0 == s1) + (s0 == s2) + (s0 == s3) + (s1 == s2) + (s1 == s3) + (s2 == s3);
-        if (with_counts) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) cnt[k] += (s0 == k) + (s1 == k) + (s2 == k) + (s3 == k);
-        }
-    }
-    if (with_counts) {
-        const int v[8] = {hb, co, cnt[0], cnt[1], cnt[2], cnt[3], cnt[4], cnt[5]};
-        block_add<8>(v, out, 1);
-    } else {
-        const int v[2] = {hb, co};
-        block_add<2>(v, out + (blockIdx.x & (spread - 1)), spread);
-    }
-}
+#include "sw_step.h"
 
 __global__ void obs_zero_kernel(DevObs* o)
 {
@@ -276,152 +244,6 @@ __global__ void obs_final_kernel(DevObs* o, const DevState* st, const DevTables*
     r.M = (double)mx / (4.0 * Nd);
     r.consistent = (st->n_hb_raw == o->acc[0] && st->n_coop == o->acc[1]) ? 1 : 0;
     r.reserved = 0;
-}
-
-// ---------------------------------------------------------------------------
-// Swendsen-Wang (Sec. II.D).
-// Bond mask per cell: bit 0 covalent +x (arm 0 of c, arm 1 of c+x), bit 1
-// covalent +y (arm 2 of c, arm 3 of c+y), bits 2..7 cooperative pairs
-// (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).  Link l uses word l of
-// Philox(c, t, 0, SWB) for l < 4 and word l-4 of Philox(c, t, 1, SWB).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool below(uint32_t w, uint64_t thr) { return (uint64_t)w < thr; }
-
-// In-cell components of the 4 arms for each of the 64 cooperative masks:
-// 2 bits per arm = smallest arm index of its component.
-__device__ void build_incell_lut(uint8_t* lut)
-{
-    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
-    if (threadIdx.x < 64) {
-        const int m = threadIdx.x;
-        int lab[4] = {0, 1, 2, 3};
-        for (int it = 0; it < 3; ++it)
-            for (int l = 0; l < 6; ++l)
-                if (m >> l & 1) {
-                    const int mn = min(lab[pa[l]], lab[pb[l]]);
-                    lab[pa[l]] = mn;
-                    lab[pb[l]] = mn;
-                }
-        lut[m] = (uint8_t)(lab[0] | lab[1] << 2 | lab[2] << 4 | lab[3] << 6);
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void sw_bonds_kernel(LatticeArgs a)
-{
-    __shared__ uint8_t lut[64];
-    build_incell_lut(lut);
-    __syncthreads();
-    const uint32_t t = a.st->t_cur;
-    const int theta = a.st->theta;
-    const uint64_t thr_s = a.tab->sw[0];
-    const uint64_t thr_e = a.tab->sw[1 + theta];
-    const bool cov_on = theta == 1 && a.jeff_sign != 0;
-    const uint32_t L = a.L;
-    const size_t N = a.N;
-    const double inv_L = 1.0 / (double)L;
-    const uint8_t* __restrict__ s = a.sigma;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
-        uint32_t x;
-        const uint32_t y = divmod(c, L, inv_L, x);
-        const uint32_t row = y * L;
-        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-        const uint32_t rp = (y + 1 == L) ? 0 : row + L;
-        const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
-        const int f0 = s[N + xp + row];
-        const int f2 = s[3 * N + x + rp];
-        const uint4 w0 = philox(c, t, 0u, kStreamSwb, a.key0, a.key1);
-        const uint4 w1 = philox(c, t, 1u, kStreamSwb, a.key0, a.key1);
-        uint32_t m = 0;
-        if (cov_on) {
-            const bool e0 = (s0 == f0) == (a.jeff_sign > 0);
-            const bool e2 = (s2 == f2) == (a.jeff_sign > 0);
-            m |= (e0 && below(w0.x, thr_e)) ? 1u : 0u;
-            m |= (e2 && below(w0.y, thr_e)) ? 2u : 0u;
-        }
-        m |= (s0 == s1 && below(w0.z, thr_s)) ? 4u : 0u;
-        m |= (s0 == s2 && below(w0.w, thr_s)) ? 8u : 0u;
-        m |= (s0 == s3 && below(w1.x, thr_s)) ? 16u : 0u;
-        m |= (s1 == s2 && below(w1.y, thr_s)) ? 32u : 0u;
-        m |= (s1 == s3 && below(w1.z, thr_s)) ? 64u : 0u;
-        m |= (s2 == s3 && below(w1.w, thr_s)) ? 128u : 0u;
-        a.mask[c] = (uint8_t)m;
-        const uint32_t l4 = lut[m >> 2];
-        a.label[c] = (l4 & 3) * (uint32_t)N + c;
-        a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
-        a.label[2 * N + c] = ((l4 >> 4) & 3) * (uint32_t)N + c;
-        a.label[3 * N + c] = ((l4 >> 6) & 3) * (uint32_t)N + c;
-    }
-}
-
-// Root of x: follow parents until a self-loop.  label[x] <= x everywhere, so
-// the chain strictly decreases and ends.
-__device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
-{
-    uint32_t p = label[x];
-    while (p != x) {
-        x = p;
-        p = label[x];
-    }
-    return x;
-}
-
-// Lock-free union by minimum index (atomicMin on the larger root).  A failed
-// attempt means the larger root got a parent meanwhile; that parent is then
-// united with the smaller root, so no connection is lost.  The largest of
-// the two roots strictly decreases each round.
-__device__ void unite(uint32_t* label, uint32_t a, uint32_t b)
-{
-    a = find_root(label, a);
-    b = find_root(label, b);
-    while (a != b) {
-        if (a > b) {
-            const uint32_t tmp = a;
-            a = b;
-            b = tmp;
-        }
-        const uint32_t old = atomicMin(label + b, a);
-        if (old == b) return;
-        b = find_root(label, old);
-        a = find_root(label, a);
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
-{
-    const uint32_t L = a.L, N = a.N;
-    const double inv_L = 1.0 / (double)L;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < N; c += gridDim.x * kBlock) {
-        const uint32_t m = a.mask[c];
-        if (!(m & 3)) continue;
-        uint32_t x;
-        const uint32_t y = divmod(c, L, inv_L, x);
-        const uint32_t row = y * L;
-        if (m & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + row);
-        if (m & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : row + L));
-    }
-}
-
-// Flatten every label to its root (the cluster minimum) and shift sigma by
-// the cluster's r = pick(w0 of Philox(root, t, 0, SWF), q), NULL -> 0.
-__global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
-{
-    const uint32_t t = a.st->t_cur;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->sw_done = 1;
-    const uint32_t N = a.N;
-    const int q = (int)a.q;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < N; c += gridDim.x * kBlock) {
-#pragma unroll
-        for (int arm = 0; arm < 4; ++arm) {
-            const uint32_t idx = arm * N + c;
-            const uint32_t r = find_root(a.label, idx);
-            a.label[idx] = r;
-            const uint32_t w = philox(r, t, 0u, kStreamSwf, a.key0, a.key1).x;
-            const int k = (w <= a.flip_lim) ? (int)((double)w * a.flip_invd) : 0;
-            int sv = a.sigma[idx] + k;
-            sv = sv >= q ? sv - q : sv;
-            a.sigma[idx] = (uint8_t)sv;
-        }
-    }
 }
 
 }  // namespace
@@ -530,9 +352,21 @@ hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, hipStream_t s)
+hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s)
 {
-    volume_batch_kernel<<<count, 64, 0, s>>>(ent);
+    volume_batch_kernel<<<count, 64, 0, s>>>(ent, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint32_t count, uint32_t total_blocks,
+                           int stage, hipStream_t s)
+{
+    switch (stage) {
+    case 0: sw_batch_kernel<0><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
+    case 1: sw_batch_kernel<1><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
+    case 2: sw_batch_kernel<2><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
+    default: sw_batch_kernel<3><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
+    }
     return hipGetLastError();
 }
 

@@ -359,11 +359,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     met_reduce(wsum, a.slots, local);
 }
 
-// One wavefront per chain: fold and open the next step of every chain.
-__global__ __launch_bounds__(64) void volume_batch_kernel(const BatchEntry* __restrict__ ent)
+// One wavefront per chain: fold and open the next step of every chain
+// (mode kVolMet before a Metropolis sweep, kVolSw before an SW step).
+__global__ __launch_bounds__(64) void volume_batch_kernel(const BatchEntry* __restrict__ ent, int mode)
 {
     __shared__ double term[40];
-    const VolArgs v = ent[blockIdx.x].va;
+    VolArgs v = ent[blockIdx.x].va;
+    v.mode = mode;
+    if (mode != kVolMet) v.met_att_add = 0;
     volume_step(v, term);
 }
 

@@ -1,0 +1,267 @@
+// Swendsen-Wang step kernels and the lattice recount (included inside the
+// kernels' namespace).  Every kernel body is a per-cell function; the
+// single-chain kernels loop over cells grid-stride, the batched kernels run one
+// cell per thread for the chain their workgroup belongs to.
+#pragma once
+
+// ---------------------------------------------------------------------------
+// Recount of N_HB_raw and N_sigma for cell c (and the state counts N_q').
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void recount_cell(const LatticeArgs& a, uint32_t c, uint32_t x, uint32_t y, int& hb,
+                                             int& co, int* cnt)
+{
+    const uint32_t L = a.L;
+    const size_t N = a.N;
+    const uint8_t* __restrict__ s = a.sigma;
+    const uint32_t row = y * L;
+    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+    const uint32_t rp = (y + 1 == L) ? 0 : row + L;
+    const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
+    hb += (s0 == s[N + xp + row]) + (s2 == s[3 * N + x + rp]);
+    co += (s0 == s1) + (s0 == s2) + (s0 == s3) + (s1 == s2) + (s1 == s3) + (s2 == s3);
+    if (cnt) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) cnt[k] += (s0 == k) + (s1 == k) + (s2 == k) + (s3 == k);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts)
+{
+    const double inv_L = 1.0 / (double)a.L;
+    int hb = 0, co = 0;
+    int cnt[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        uint32_t x;
+        const uint32_t y = divmod(c, a.L, inv_L, x);
+        recount_cell(a, c, x, y, hb, co, with_counts ? cnt : nullptr);
+    }
+    if (with_counts) {
+        const int v[8] = {hb, co, cnt[0], cnt[1], cnt[2], cnt[3], cnt[4], cnt[5]};
+        block_add<8>(v, out, 1);
+    } else {
+        const int v[2] = {hb, co};
+        block_add<2>(v, out + (blockIdx.x & (spread - 1)), spread);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Swendsen-Wang (Sec. II.D).
+// Bond mask per cell: bit 0 covalent +x (arm 0 of c, arm 1 of c+x), bit 1
+// covalent +y (arm 2 of c, arm 3 of c+y), bits 2..7 cooperative pairs
+// (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).  Link l uses word l of
+// Philox(c, t, 0, SWB) for l < 4 and word l-4 of Philox(c, t, 1, SWB).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool below(uint32_t w, uint64_t thr) { return (uint64_t)w < thr; }
+
+// In-cell components of the 4 arms for each of the 64 cooperative masks:
+// 2 bits per arm = smallest arm index of its component.
+__device__ void build_incell_lut(uint8_t* lut)
+{
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
+    if (threadIdx.x < 64) {
+        const int m = threadIdx.x;
+        int lab[4] = {0, 1, 2, 3};
+        for (int it = 0; it < 3; ++it)
+            for (int l = 0; l < 6; ++l)
+                if (m >> l & 1) {
+                    const int mn = min(lab[pa[l]], lab[pb[l]]);
+                    lab[pa[l]] = mn;
+                    lab[pb[l]] = mn;
+                }
+        lut[m] = (uint8_t)(lab[0] | lab[1] << 2 | lab[2] << 4 | lab[3] << 6);
+    }
+}
+
+struct SwBondCtx {
+    uint32_t t;
+    uint64_t thr_s, thr_e;
+    bool cov_on;
+};
+
+__device__ __forceinline__ SwBondCtx sw_ctx(const LatticeArgs& a)
+{
+    const int theta = a.st->theta;
+    SwBondCtx k;
+    k.t = a.st->t_cur;
+    k.thr_s = a.tab->sw[0];
+    k.thr_e = a.tab->sw[1 + theta];
+    k.cov_on = theta == 1 && a.jeff_sign != 0;
+    return k;
+}
+
+// Bond activation of cell c, and its labels initialised to the in-cell
+// cooperative components (smallest arm of each component).
+__device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBondCtx& k, const uint8_t* lut,
+                                              uint32_t c, uint32_t x, uint32_t y)
+{
+    const uint32_t L = a.L;
+    const size_t N = a.N;
+    const uint8_t* __restrict__ s = a.sigma;
+    const uint32_t row = y * L;
+    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+    const uint32_t rp = (y + 1 == L) ? 0 : row + L;
+    const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
+    const int f0 = s[N + xp + row];
+    const int f2 = s[3 * N + x + rp];
+    const uint4 w0 = philox(c, k.t, 0u, kStreamSwb, a.key0, a.key1);
+    const uint4 w1 = philox(c, k.t, 1u, kStreamSwb, a.key0, a.key1);
+    uint32_t m = 0;
+    if (k.cov_on) {
+        const bool e0 = (s0 == f0) == (a.jeff_sign > 0);
+        const bool e2 = (s2 == f2) == (a.jeff_sign > 0);
+        m |= (e0 && below(w0.x, k.thr_e)) ? 1u : 0u;
+        m |= (e2 && below(w0.y, k.thr_e)) ? 2u : 0u;
+    }
+    m |= (s0 == s1 && below(w0.z, k.thr_s)) ? 4u : 0u;
+    m |= (s0 == s2 && below(w0.w, k.thr_s)) ? 8u : 0u;
+    m |= (s0 == s3 && below(w1.x, k.thr_s)) ? 16u : 0u;
+    m |= (s1 == s2 && below(w1.y, k.thr_s)) ? 32u : 0u;
+    m |= (s1 == s3 && below(w1.z, k.thr_s)) ? 64u : 0u;
+    m |= (s2 == s3 && below(w1.w, k.thr_s)) ? 128u : 0u;
+    a.mask[c] = (uint8_t)m;
+    const uint32_t l4 = lut[m >> 2];
+    a.label[c] = (l4 & 3) * (uint32_t)N + c;
+    a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
+    a.label[2 * N + c] = ((l4 >> 4) & 3) * (uint32_t)N + c;
+    a.label[3 * N + c] = ((l4 >> 6) & 3) * (uint32_t)N + c;
+}
+
+__global__ __launch_bounds__(kBlock) void sw_bonds_kernel(LatticeArgs a)
+{
+    __shared__ uint8_t lut[64];
+    build_incell_lut(lut);
+    __syncthreads();
+    const SwBondCtx k = sw_ctx(a);
+    const double inv_L = 1.0 / (double)a.L;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        uint32_t x;
+        const uint32_t y = divmod(c, a.L, inv_L, x);
+        sw_bonds_cell(a, k, lut, c, x, y);
+    }
+}
+
+// Root of x: follow parents until a self-loop.  label[x] <= x everywhere, so
+// the chain strictly decreases and ends.
+__device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
+{
+    uint32_t p = label[x];
+    while (p != x) {
+        x = p;
+        p = label[x];
+    }
+    return x;
+}
+
+// Lock-free union by minimum index (atomicMin on the larger root).  A failed
+// attempt means the larger root got a parent meanwhile; that parent is then
+// united with the smaller root, so no connection is lost.  The largest of
+// the two roots strictly decreases each round.
+__device__ void unite(uint32_t* label, uint32_t a, uint32_t b)
+{
+    a = find_root(label, a);
+    b = find_root(label, b);
+    while (a != b) {
+        if (a > b) {
+            const uint32_t tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const uint32_t old = atomicMin(label + b, a);
+        if (old == b) return;
+        b = find_root(label, old);
+        a = find_root(label, a);
+    }
+}
+
+__device__ __forceinline__ void sw_union_cell(const LatticeArgs& a, uint32_t c, uint32_t x, uint32_t y)
+{
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t m = a.mask[c];
+    if (!(m & 3)) return;
+    const uint32_t row = y * L;
+    if (m & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + row);
+    if (m & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : row + L));
+}
+
+__global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
+{
+    const double inv_L = 1.0 / (double)a.L;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
+        uint32_t x;
+        const uint32_t y = divmod(c, a.L, inv_L, x);
+        sw_union_cell(a, c, x, y);
+    }
+}
+
+// Flatten the labels of cell c to their roots (the cluster minima) and shift
+// sigma by the cluster's r = pick(w0 of Philox(root, t, 0, SWF), q), NULL -> 0.
+__device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, uint32_t c)
+{
+    const uint32_t N = a.N;
+    const int q = (int)a.q;
+#pragma unroll
+    for (int arm = 0; arm < 4; ++arm) {
+        const uint32_t idx = arm * N + c;
+        const uint32_t r = find_root(a.label, idx);
+        a.label[idx] = r;
+        const uint32_t w = philox(r, t, 0u, kStreamSwf, a.key0, a.key1).x;
+        const int k = (w <= a.flip_lim) ? (int)((double)w * a.flip_invd) : 0;
+        int sv = a.sigma[idx] + k;
+        sv = sv >= q ? sv - q : sv;
+        a.sigma[idx] = (uint8_t)sv;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
+{
+    const uint32_t t = a.st->t_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->sw_done = 1;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) sw_flip_cell(a, t, c);
+}
+
+// ---------------------------------------------------------------------------
+// Batched Swendsen-Wang: workgroup b belongs to the chain c with
+// swstart[c] <= b < swstart[c+1] and covers its cells 256 (b - swstart[c]) ..
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t count, uint32_t b)
+{
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// stage 0 bonds, 1 union, 2 flip, 3 recount
+template <int STAGE>
+__global__ __launch_bounds__(kBlock) void sw_batch_kernel(const BatchEntry* __restrict__ ent,
+                                                          const uint32_t* __restrict__ swstart, uint32_t count)
+{
+    __shared__ uint8_t lut[64];
+    const uint32_t ch = batch_chain(swstart, count, blockIdx.x);
+    const LatticeArgs a = ent[ch].la;
+    const uint32_t local = blockIdx.x - swstart[ch];
+    const uint32_t c = local * kBlock + threadIdx.x;
+    const bool in = c < a.N;
+    uint32_t x = 0, y = 0;
+    if (in) y = divmod(c, a.L, 1.0 / (double)a.L, x);
+    if (STAGE == 0) {
+        build_incell_lut(lut);
+        __syncthreads();
+        const SwBondCtx k = sw_ctx(a);
+        if (in) sw_bonds_cell(a, k, lut, c, x, y);
+    } else if (STAGE == 1) {
+        if (in) sw_union_cell(a, c, x, y);
+    } else if (STAGE == 2) {
+        const uint32_t t = a.st->t_cur;
+        if (local == 0 && threadIdx.x == 0) a.st->sw_done = 1;
+        if (in) sw_flip_cell(a, t, c);
+    } else {
+        int hb = 0, co = 0;
+        if (in) recount_cell(a, c, x, y, hb, co, nullptr);
+        const int v[2] = {hb, co};
+        block_add<2>(v, a.slots + (local & (kSlots - 1)), kSlots);
+    }
+}

@@ -23,7 +23,8 @@ CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
 EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
            "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_batch_desc_bytes", "cvf_batch_create",
-           "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_autotune", "cvf_batch_destroy"]
+           "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
+           "cvf_batch_destroy"]
 
 
 class CvfError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.cvf_batch_set_rows.argtypes = [vp, ctypes.c_int32, vp]
         L.cvf_batch_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp]
+        L.cvf_batch_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_batch_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
         L.cvf_batch_destroy.argtypes = [vp]
         L.cvf_strerror.argtypes = [ctypes.c_int]
@@ -212,6 +214,10 @@ def cvf_batch_metropolis_sweeps(b, nsweeps: int, graph_block: int = 0, stream=No
     _check("cvf_batch_metropolis_sweeps", lib().cvf_batch_metropolis_sweeps(b, nsweeps, graph_block, _stream(stream)))
 
 
+def cvf_batch_sw_steps(b, nsteps: int, stream=None):
+    _check("cvf_batch_sw_steps", lib().cvf_batch_sw_steps(b, nsteps, _stream(stream)))
+
+
 def cvf_batch_autotune(b, sweeps: int, stream=None) -> int:
     r = ctypes.c_int32()
     _check("cvf_batch_autotune", lib().cvf_batch_autotune(b, sweeps, _stream(stream), ctypes.byref(r)))
@@ -235,6 +241,10 @@ class Batch:
 
     def metropolis(self, n, graph_block=0):
         cvf_batch_metropolis_sweeps(self.h, n, graph_block, self.stream)
+        return self
+
+    def sw(self, n):
+        cvf_batch_sw_steps(self.h, n, self.stream)
         return self
 
     def set_rows(self, rows):

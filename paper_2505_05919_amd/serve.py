@@ -4,8 +4,9 @@ Jobs (L, T, P, nsteps, algorithm, seed) arrive over time.  The server admits
 them in arrival order while their device footprint fits the memory budget and
 a slot is free, keeps every admitted lattice resident in HBM, and advances all
 resident jobs together in quanta: the Metropolis jobs as one batched launch
-per colour phase (``cvf_batch_*``), the Swendsen-Wang jobs on a second stream
-so that their kernels overlap with the batch.  Jobs that finish leave between
+per colour phase, the Swendsen-Wang jobs as one batched launch per SW stage
+(``cvf_batch_*``) on a second stream, so that the two batches overlap on the
+device.  Jobs that finish leave between
 quanta and queued jobs take their place, so requests that arrive while others
 run are admitted as memory and slots free up.
 
@@ -36,6 +37,7 @@ class Running:
     chain: cvf.Chain
     done: int = 0
     admitted_at: float = 0.0
+    t_ref: float = 0.0          # latency origin: the arrival (realtime) or the release
 
 
 @dataclass
@@ -45,14 +47,15 @@ class Record:
     completed: float
     obs: dict
     digest: str = ""
+    t_ref: float = 0.0
 
     @property
     def latency(self):
-        return self.completed - self.job.arrival
+        return self.completed - self.t_ref
 
     @property
     def queueing(self):
-        return self.admitted - self.job.arrival
+        return self.admitted - self.t_ref
 
 
 @dataclass
@@ -63,6 +66,9 @@ class Server:
     graph_block: int = 0                # >0: batched sweeps replay a hipGraph of this many
     keep_digest: bool = False
     records: list = field(default_factory=list)
+    peak_resident_bytes: int = 0
+    peak_resident_jobs: int = 0
+    quanta: int = 0
 
     def run(self, jobs: list[Job], realtime: bool = True) -> list[Record]:
         """Serve `jobs` (sorted by arrival).  realtime: arrivals are released
@@ -79,6 +85,8 @@ class Server:
         used = 0
         batch = None
         batch_members: tuple = ()
+        swb = None
+        swb_members: tuple = ()
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0     # noqa: E731
 
@@ -97,8 +105,10 @@ class Server:
                 st = stream_s if job.algo == "sw" else stream_b
                 with torch.cuda.stream(st):
                     ch = cvf.Chain(p, mask, stream=st)
-                running.append(Running(job, ch, 0, now()))
+                running.append(Running(job, ch, 0, now(), job.arrival if realtime else 0.0))
                 used += fp
+                self.peak_resident_bytes = max(self.peak_resident_bytes, used)
+                self.peak_resident_jobs = max(self.peak_resident_jobs, len(running))
             if not running:
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now(), 0.002)))
@@ -117,30 +127,45 @@ class Server:
                 batch.metropolis(steps, graph_block=self.graph_block if steps % max(1, self.graph_block) == 0 else 0)
                 for r in met:
                     r.done += steps
-            for r in sws:
-                n = min(self.quantum, r.job.nsteps - r.done)
-                r.chain.sw(n)
-                r.done += n
+            if sws:
+                n = min(self.quantum, min(r.job.nsteps - r.done for r in sws))
+                members = tuple(id(r) for r in sws)
+                if members != swb_members:
+                    if swb is not None:
+                        swb.close()
+                    swb = cvf.Batch([r.chain for r in sws], stream=stream_s)
+                    swb_members = members
+                swb.sw(n)
+                for r in sws:
+                    r.done += n
             torch.cuda.synchronize()
+            self.quanta += 1
             tdone = now()
             still = []
             for r in running:
                 if r.done >= r.job.nsteps:
                     o = r.chain.obs()
                     dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if self.keep_digest else ""
-                    self.records.append(Record(r.job, r.admitted_at, tdone, o, dg))
+                    self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
                     used -= footprint(r.job)
                     if r.job.algo == "met":
                         batch_members = ()          # membership changes
+                    else:
+                        swb_members = ()
                     r.chain.close()
                 else:
                     still.append(r)
             if batch is not None and batch_members == ():
                 batch.close()
                 batch = None
+            if swb is not None and swb_members == ():
+                swb.close()
+                swb = None
             running = still
         if batch is not None:
             batch.close()
+        if swb is not None:
+            swb.close()
         return self.records
 
 
@@ -179,7 +204,7 @@ def summarize(records: list[Record]) -> dict:
     q = np.array([r.queueing for r in records])
     upd = sum(4 * r.job.L ** 2 * r.job.nsteps for r in records if r.job.algo == "met")
     cells = sum(r.job.L ** 2 * r.job.nsteps for r in records if r.job.algo == "sw")
-    span = max(r.completed for r in records) - min(r.job.arrival for r in records)
+    span = max(r.completed for r in records) - min(r.t_ref for r in records)
     return {"jobs": len(records), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "queue_p50_s": float(np.percentile(q, 50)), "queue_p99_s": float(np.percentile(q, 99)),
             "makespan_s": span, "met_updates_per_ns": upd / span / 1e9, "sw_cell_steps_per_ns": cells / span / 1e9}

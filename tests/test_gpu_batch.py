@@ -125,3 +125,58 @@ def test_batch_rejects_mixed_q(cvf):
         cvf.Batch([a, b])
     a.close()
     b.close()
+
+
+def test_batch_sw_equals_alone(cvf):
+    jobs = mixed_jobs(20, seed=5)
+    say(f"case batch sw Ls={[j[0] for j in jobs]}")
+    alone = []
+    for L, T, P, s in jobs:
+        ch = cvf.Chain(params(cvf, L, T, P, s))
+        ch.sw(4).metropolis(2).sw(3)
+        alone.append((digest(ch), ch.obs(), ch.labels().cpu().numpy().copy()))
+        ch.close()
+    chains = [cvf.Chain(params(cvf, L, T, P, s)) for L, T, P, s in jobs]
+    b = cvf.Batch(chains)
+    b.sw(4).metropolis(2).sw(3)
+    for k, ch in enumerate(chains):
+        assert digest(ch) == alone[k][0], (k, jobs[k])
+        assert ch.obs() == alone[k][1], (k, jobs[k])
+        assert np.array_equal(ch.labels().cpu().numpy(), alone[k][2]), (k, jobs[k])
+    b.close()
+    for ch in chains:
+        ch.close()
+
+
+def test_batch_sw_vs_oracle(cvf, oracle_mod):
+    jobs = [(2, 300.0, 0.1, 31), (10, 270.0, 50.0, 32), (34, 330.0, 3000.0, 33)]
+    chains, orcs = [], []
+    for L, T, P, s in jobs:
+        op = oracle_mod.params_from_si(T, P, L=L, seed=s)
+        p = cvf.cvf_params()
+        for k, v in op.as_dict().items():
+            setattr(p, k, v)
+        chains.append(cvf.Chain(p))
+        orcs.append(oracle_mod.Chain(op))
+    b = cvf.Batch(chains)
+    b.sw(6)
+    for ch, oc in zip(chains, orcs):
+        oc.sw(6)
+        assert np.array_equal(ch.sigma.cpu().numpy(), oc.sigma())
+        assert np.array_equal(ch.labels().cpu().numpy().view(np.uint32), oc.labels())
+        og, oo = ch.obs(), oc.obs()
+        for k in ("step", "n_hb_raw", "n_coop", "vol_accepted", "count"):
+            assert og[k] == oo[k], k
+    b.close()
+    for ch in chains:
+        ch.close()
+
+
+def test_batch_sw_needs_workspace(cvf):
+    a = cvf.Chain(params(cvf, 8, 300.0, 0.1, 1), cvf.CVF_ALGO_METROPOLIS)
+    b = cvf.Batch([a])
+    with pytest.raises(cvf.CvfError) as e:
+        b.sw(1)
+    assert e.value.code == cvf.CVF_ENOMEM
+    b.close()
+    a.close()

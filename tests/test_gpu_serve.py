@@ -1,0 +1,57 @@
+"""Continuous-batching server: every job's result is identical alone and in
+the mix; admission respects the memory budget; queued jobs join while
+others run."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05919_amd import serve as mod
+    return mod
+
+
+def small_stream(n=28):
+    from paper_2505_05919_amd.workloads import c5_stream
+    return c5_stream(n_jobs=n, rate=400.0, seed=21, nsteps_range=(5, 60), L_range=(4, 160))
+
+
+def test_served_equals_alone(serve):
+    jobs = small_stream()
+    assert {j.algo for j in jobs} == {"met", "sw"}
+    budget = 3 * max(serve.footprint(j) for j in jobs)          # only a few jobs fit at once
+    srv = serve.Server(memory_budget=budget, max_slots=8, quantum=7, keep_digest=True)
+    recs = srv.run(jobs, realtime=True)
+    assert len(recs) == len(jobs)
+    assert srv.peak_resident_bytes <= budget
+    assert 1 < srv.peak_resident_jobs <= 8
+    by_seed = {r.job.seed: r for r in recs}
+    for j in jobs:
+        o, dg, _ = serve.run_alone(j)
+        r = by_seed[j.seed]
+        assert r.digest == dg, j
+        assert r.obs == o, j
+        assert r.completed >= r.admitted >= 0
+
+
+def test_served_all_at_once_and_graphs(serve):
+    jobs = [j for j in small_stream(16) if j.algo == "met"]
+    srv = serve.Server(memory_budget=1 << 34, max_slots=64, quantum=4, graph_block=4, keep_digest=True)
+    recs = srv.run(jobs, realtime=False)
+    for r in recs:
+        o, dg, _ = serve.run_alone(r.job)
+        assert r.digest == dg and r.obs == o
+    s = serve.summarize(recs)
+    assert s["jobs"] == len(jobs) and s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_fcfs_latency_model(serve):
+    from paper_2505_05919_amd.workloads import Job
+    jobs = [Job(8, 300.0, 0.1, 1, "met", 1, a) for a in (0.0, 0.5, 0.6, 3.0)]
+    lat = serve.fcfs_latencies(jobs, [1.0, 1.0, 1.0, 1.0])
+    assert np.allclose(lat, [1.0, 1.5, 2.4, 1.0])
