@@ -146,6 +146,13 @@ int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
  * d_out.  CVF_ESTATE if no Swendsen-Wang step has run.  Asynchronous. */
 int cvf_labels(cvf_state *st, uint32_t *d_out, void *stream);
 
+/* Step limit: steps with index >= stop_at (counted from 0 at cvf_init) are
+ * not performed -- later calls, single or batched, leave the chain as it is
+ * (sigma, v, counters).  Default: no limit.  Lets a batch run fixed-length
+ * quanta while every chain stops exactly at its own step count.  stop_at >= 0.
+ * Asynchronous. */
+int cvf_set_stop(cvf_state *st, int64_t stop_at, void *stream);
+
 /* Test hook: the host-computed acceptance tables of this chain.
  * met[theta][dh+1][dc+3]: accept iff thr == 0xFFFFFFFF or word < thr.
  * sw[0] cooperative bond threshold, sw[1], sw[2] covalent thresholds for

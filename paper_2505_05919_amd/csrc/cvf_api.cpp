@@ -270,7 +270,7 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     hipError_t e = hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, st->dtab, p->v_init, s);
     if (e == hipSuccess && !(p->flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(a, s);
-    if (e == hipSuccess) e = launch_recount(a, st->slots, kSlots, 0, s);
+    if (e == hipSuccess) e = launch_recount(a, st->slots, kSlots, 0, 0, s);
     if (e != hipSuccess) {
         delete st;
         return CVF_EHIP;
@@ -307,7 +307,7 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
         TIMED(CVF_K_SW_BONDS, launch_sw_bonds(st->la, s));
         TIMED(CVF_K_SW_UNION, launch_sw_union(st->la, s));
         TIMED(CVF_K_SW_FLIP, launch_sw_flip(st->la, s));
-        TIMED(CVF_K_RECOUNT, launch_recount(st->la, st->slots, kSlots, 0, s));
+        TIMED(CVF_K_RECOUNT, launch_recount(st->la, st->slots, kSlots, 0, 1, s));
     }
     return CVF_OK;
 }
@@ -320,7 +320,7 @@ int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
     v.mode = kVolFold;
     hipError_t e = launch_volume(v, s);
     if (e == hipSuccess) e = launch_obs_zero(st->dobs, s);
-    if (e == hipSuccess) e = launch_recount(st->la, st->dobs->acc, 1, 1, s);
+    if (e == hipSuccess) e = launch_recount(st->la, st->dobs->acc, 1, 1, 0, s);
     if (e == hipSuccess)
         e = launch_obs_final(st->dobs, st->dst, st->dtab, (double)st->N, st->p.J, st->p.Jsigma, st->p.P,
                              st->p.vHB, s);
@@ -343,6 +343,12 @@ int cvf_labels(cvf_state* st, uint32_t* d_out, void* stream)
     if (e != hipSuccess) return CVF_EHIP;
     if (!done) return CVF_ESTATE;
     return hip_status(hipMemcpyAsync(d_out, st->label, 4ull * st->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+}
+
+int cvf_set_stop(cvf_state* st, int64_t stop_at, void* stream)
+{
+    if (!st || stop_at < 0) return CVF_EINVAL;
+    return hip_status(launch_set_stop(st->dst, stop_at, (hipStream_t)stream));
 }
 
 int cvf_tables(const cvf_state* st, uint32_t met[2][3][7], uint64_t sw[3])

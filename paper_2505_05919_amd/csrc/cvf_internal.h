@@ -30,7 +30,8 @@ struct DevState {
     uint32_t t_cur;          // step being executed (Philox counter word 1)
     int32_t theta;           // 1 liquid (v < 2), 0 gas
     int32_t sw_done;         // a Swendsen-Wang step has produced labels
-    int32_t pad_;
+    int32_t skip;            // 1: the step limit is reached, step kernels do nothing
+    int64_t stop_at;         // no step with index >= stop_at is performed
 };
 
 // Host-computed constants copied to the workspace at init.
@@ -104,10 +105,13 @@ struct BatchEntry {
 
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
 hipError_t launch_state_init(DevState* st, int64_t* slots, const DevTables* tab, double v_init, hipStream_t s);
+hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
-hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, hipStream_t s);
+// step_gate: the recount closes an SW step and is skipped with it.
+hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
+                          hipStream_t s);
 hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
 hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
                             double Jsigma, double P, double vHB, hipStream_t s);

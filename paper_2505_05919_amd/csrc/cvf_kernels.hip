@@ -105,7 +105,8 @@ __global__ void state_init_kernel(DevState* st, int64_t* slots, const DevTables*
         st->t_cur = 0;
         st->theta = v_init < 2.0 ? 1 : 0;
         st->sw_done = 0;
-        st->pad_ = 0;
+        st->skip = 0;
+        st->stop_at = INT64_MAX;
     }
 }
 
@@ -156,6 +157,15 @@ __device__ void volume_step(const VolArgs& a, double* term)
         }
         return;
     }
+    if (st->t_next >= st->stop_at) {          // step limit: fold only, the step kernels skip
+        if (lane == 0) {
+            st->n_hb_raw += hb;
+            st->n_coop += co;
+            st->met_acc += ac;
+            st->skip = 1;
+        }
+        return;
+    }
     const uint32_t t = (uint32_t)st->t_next;
     const uint4 w = philox(0u, t, 0u, kStreamVol, a.key0, a.key1);
     const double u = (double)((int64_t)2 * (int64_t)w.x + 1 - 4294967296LL) * (1.0 / 4294967296.0);
@@ -171,6 +181,7 @@ __device__ void volume_step(const VolArgs& a, double* term)
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (lane != 0) return;
+    st->skip = 0;
     st->n_hb_raw += hb;
     st->n_coop += co;
     st->met_acc += ac;
@@ -300,9 +311,21 @@ hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, hipStream_t s)
+__global__ void set_stop_kernel(DevState* st, int64_t stop_at)
 {
-    recount_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a, out, spread, with_counts);
+    if (threadIdx.x == 0) st->stop_at = stop_at;
+}
+
+hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)
+{
+    set_stop_kernel<<<1, 64, 0, s>>>(st, stop_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
+                          hipStream_t s)
+{
+    recount_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a, out, spread, with_counts, step_gate);
     return hipGetLastError();
 }
 

@@ -280,6 +280,7 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, const u
 template <int Q, int KAPPA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_sweep4_kernel(LatticeArgs a)
 {
+    if (a.st->skip) return;                                // step limit reached
     __shared__ uint2 tbl[32];
     met_table(a, tbl);
     const uint32_t wsum = met_quad_block<Q, KAPPA>(a, tbl, a.st->t_cur, blockIdx.x, blockIdx.y);
@@ -323,6 +324,7 @@ __device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, const u
 template <int Q>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_sweep_kernel(LatticeArgs a, int colour)
 {
+    if (a.st->skip) return;                                // step limit reached
     // 32 entries: indices d + 16 for d in -15..15, so that even out-of-range
     // bond indices (a caller-supplied configuration) cannot read outside it.
     __shared__ uint2 tbl[32];
@@ -349,6 +351,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         else hi = mid;
     }
     const LatticeArgs a = ent[lo].la;
+    if (a.st->skip) return;                                // step limit reached
     const uint32_t local = blockIdx.x - start[lo];
     const uint32_t gx = ent[lo].groups_x;
     const uint32_t by = local / gx, bx = local - by * gx;

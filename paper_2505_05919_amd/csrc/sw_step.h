@@ -25,8 +25,10 @@ __device__ __forceinline__ void recount_cell(const LatticeArgs& a, uint32_t c, u
     }
 }
 
-__global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts)
+__global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts,
+                                                         int step_gate)
 {
+    if (step_gate && a.st->skip) return;
     const double inv_L = 1.0 / (double)a.L;
     int hb = 0, co = 0;
     int cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -128,6 +130,7 @@ __device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBond
 
 __global__ __launch_bounds__(kBlock) void sw_bonds_kernel(LatticeArgs a)
 {
+    if (a.st->skip) return;
     __shared__ uint8_t lut[64];
     build_incell_lut(lut);
     __syncthreads();
@@ -185,6 +188,7 @@ __device__ __forceinline__ void sw_union_cell(const LatticeArgs& a, uint32_t c, 
 
 __global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
 {
+    if (a.st->skip) return;
     const double inv_L = 1.0 / (double)a.L;
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
         uint32_t x;
@@ -214,6 +218,7 @@ __device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, u
 
 __global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
 {
+    if (a.st->skip) return;
     const uint32_t t = a.st->t_cur;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.st->sw_done = 1;
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) sw_flip_cell(a, t, c);
@@ -242,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void sw_batch_kernel(const BatchEntry* __re
     __shared__ uint8_t lut[64];
     const uint32_t ch = batch_chain(swstart, count, blockIdx.x);
     const LatticeArgs a = ent[ch].la;
+    if (a.st->skip) return;
     const uint32_t local = blockIdx.x - swstart[ch];
     const uint32_t c = local * kBlock + threadIdx.x;
     const bool in = c < a.N;

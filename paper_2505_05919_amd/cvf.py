@@ -22,7 +22,7 @@ CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
 
 EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
-           "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_batch_desc_bytes", "cvf_batch_create",
+           "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_set_stop", "cvf_batch_desc_bytes", "cvf_batch_create",
            "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
            "cvf_batch_destroy"]
 
@@ -75,6 +75,7 @@ def lib():
         L.cvf_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_observables.argtypes = [vp, ctypes.POINTER(cvf_obs), vp]
         L.cvf_labels.argtypes = [vp, vp, vp]
+        L.cvf_set_stop.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]
         L.cvf_timing_enable.argtypes = [vp, ctypes.c_int]
         L.cvf_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
@@ -167,6 +168,10 @@ def cvf_labels(st, out, stream=None):
     op, _ = _devptr(out, "torch.int32", 4)
     _check("cvf_labels", lib().cvf_labels(st, op, _stream(stream)))
     return out
+
+
+def cvf_set_stop(st, stop_at: int, stream=None):
+    _check("cvf_set_stop", lib().cvf_set_stop(st, stop_at, _stream(stream)))
 
 
 def cvf_tables(st):
@@ -297,6 +302,10 @@ class Chain:
 
     def tables(self):
         return cvf_tables(self.h)
+
+    def set_stop(self, stop_at):
+        cvf_set_stop(self.h, stop_at, self.stream)
+        return self
 
     def close(self):
         if getattr(self, "h", None) is not None:

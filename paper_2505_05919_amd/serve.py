@@ -105,6 +105,7 @@ class Server:
                 st = stream_s if job.algo == "sw" else stream_b
                 with torch.cuda.stream(st):
                     ch = cvf.Chain(p, mask, stream=st)
+                    ch.set_stop(job.nsteps)            # quanta may overshoot; the chain stops exactly
                 running.append(Running(job, ch, 0, now(), job.arrival if realtime else 0.0))
                 used += fp
                 self.peak_resident_bytes = max(self.peak_resident_bytes, used)
@@ -117,7 +118,7 @@ class Server:
             sws = [r for r in running if r.job.algo == "sw"]
             # one quantum: every resident job advances by min(quantum, remaining) steps
             if met:
-                steps = min(self.quantum, min(r.job.nsteps - r.done for r in met))
+                steps = min(self.quantum, max(r.job.nsteps - r.done for r in met))
                 members = tuple(id(r) for r in met)
                 if members != batch_members:
                     if batch is not None:
@@ -126,9 +127,9 @@ class Server:
                     batch_members = members
                 batch.metropolis(steps, graph_block=self.graph_block if steps % max(1, self.graph_block) == 0 else 0)
                 for r in met:
-                    r.done += steps
+                    r.done = min(r.done + steps, r.job.nsteps)
             if sws:
-                n = min(self.quantum, min(r.job.nsteps - r.done for r in sws))
+                n = min(self.quantum, max(r.job.nsteps - r.done for r in sws))
                 members = tuple(id(r) for r in sws)
                 if members != swb_members:
                     if swb is not None:
@@ -137,7 +138,7 @@ class Server:
                     swb_members = members
                 swb.sw(n)
                 for r in sws:
-                    r.done += n
+                    r.done = min(r.done + n, r.job.nsteps)
             torch.cuda.synchronize()
             self.quanta += 1
             tdone = now()

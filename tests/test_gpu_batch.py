@@ -180,3 +180,29 @@ def test_batch_sw_needs_workspace(cvf):
     assert e.value.code == cvf.CVF_ENOMEM
     b.close()
     a.close()
+
+
+def test_step_limit(cvf):
+    """cvf_set_stop: a batch runs more steps than some chains need; each chain
+    ends exactly where its own run of `stop` steps ends, whatever follows."""
+    jobs = mixed_jobs(12, seed=13)
+    stops = [3 + (k % 5) for k in range(len(jobs))]
+    chains = [cvf.Chain(params(cvf, L, T, P, s)) for L, T, P, s in jobs]
+    for ch, st in zip(chains, stops):
+        ch.set_stop(st)
+    b = cvf.Batch(chains)
+    b.metropolis(4).sw(2).metropolis(3)
+    chains[0].metropolis(5)                     # single-chain calls respect the limit too
+    for k, ((L, T, P, s), ch) in enumerate(zip(jobs, chains)):
+        ref = cvf.Chain(params(cvf, L, T, P, s))
+        n = stops[k]
+        m1 = min(n, 4)
+        m2 = min(n - m1, 2)
+        m3 = min(n - m1 - m2, 3)
+        ref.metropolis(m1).sw(m2).metropolis(m3)
+        assert digest(ch) == digest(ref), k
+        assert ch.obs() == ref.obs(), k
+        ref.close()
+    b.close()
+    for ch in chains:
+        ch.close()
