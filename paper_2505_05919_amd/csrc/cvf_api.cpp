@@ -304,8 +304,8 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
     v.mode = kVolSw;
     for (int64_t i = 0; i < nsteps; ++i) {
         TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        TIMED(CVF_K_SW_BONDS, launch_sw_bonds(st->la, s));
-        TIMED(CVF_K_SW_UNION, launch_sw_union(st->la, s));
+        TIMED(CVF_K_SW_BONDS, launch_sw_tiles(st->la, s));
+        TIMED(CVF_K_SW_UNION, launch_sw_union_edges(st->la, s));
         TIMED(CVF_K_SW_FLIP, launch_sw_flip(st->la, s));
         TIMED(CVF_K_RECOUNT, launch_recount(st->la, st->slots, kSlots, 0, 1, s));
     }

@@ -342,6 +342,21 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
     return hipGetLastError();
 }
 
+hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s)
+{
+    const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
+    sw_tile_kernel<<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s)
+{
+    const uint32_t ncx = (a.L + kTW - 1) / kTW, ncy = (a.L + kTH - 1) / kTH;
+    const uint64_t n = (uint64_t)(ncx + ncy) * a.L;
+    sw_union_edges_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, ncx, ncy);
+    return hipGetLastError();
+}
+
 hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s)
 {
     sw_bonds_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);

@@ -91,10 +91,9 @@ __device__ __forceinline__ SwBondCtx sw_ctx(const LatticeArgs& a)
     return k;
 }
 
-// Bond activation of cell c, and its labels initialised to the in-cell
-// cooperative components (smallest arm of each component).
-__device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBondCtx& k, const uint8_t* lut,
-                                              uint32_t c, uint32_t x, uint32_t y)
+// Bond activation of cell c: the 8-bit link mask (also stored in mask[c]).
+__device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwBondCtx& k, uint32_t c, uint32_t x,
+                                                 uint32_t y)
 {
     const uint32_t L = a.L;
     const size_t N = a.N;
@@ -121,6 +120,16 @@ __device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBond
     m |= (s1 == s3 && below(w1.z, k.thr_s)) ? 64u : 0u;
     m |= (s2 == s3 && below(w1.w, k.thr_s)) ? 128u : 0u;
     a.mask[c] = (uint8_t)m;
+    return m;
+}
+
+// Bond activation of cell c, and its labels initialised to the in-cell
+// cooperative components (smallest arm of each component).
+__device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBondCtx& k, const uint8_t* lut,
+                                              uint32_t c, uint32_t x, uint32_t y)
+{
+    const size_t N = a.N;
+    const uint32_t m = sw_bond_mask(a, k, c, x, y);
     const uint32_t l4 = lut[m >> 2];
     a.label[c] = (l4 & 3) * (uint32_t)N + c;
     a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
@@ -194,6 +203,117 @@ __global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
         uint32_t x;
         const uint32_t y = divmod(c, a.L, inv_L, x);
         sw_union_cell(a, c, x, y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled bond activation + local labelling.  A workgroup owns a tile of
+// kTW x kTH cells: it activates the bonds of every cell of the tile (same
+// decisions as sw_bonds_cell), unites the covalent links that stay inside the
+// tile in LDS (lock-free, ds_min atomics on local indices, whose order is
+// the order of the global flat indices), and writes for every bond index the
+// global index of its tile-local component minimum.  Links that cross a tile
+// edge (or the periodic wrap) are left to sw_union_edges_kernel.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTW = 64, kTH = 16, kTC = kTW * kTH;       // tile: 1024 cells, 4096 bond indices
+
+__device__ __forceinline__ uint32_t find_root_lds(const uint32_t* lab, uint32_t x)
+{
+    uint32_t p = lab[x];
+    while (p != x) {
+        x = p;
+        p = lab[x];
+    }
+    return x;
+}
+
+__device__ __forceinline__ void unite_lds(uint32_t* lab, uint32_t a, uint32_t b)
+{
+    a = find_root_lds(lab, a);
+    b = find_root_lds(lab, b);
+    while (a != b) {
+        if (a > b) {
+            const uint32_t tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const uint32_t old = atomicMin(lab + b, a);
+        if (old == b) return;
+        b = find_root_lds(lab, old);
+        a = find_root_lds(lab, a);
+    }
+}
+
+__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+{
+    if (a.st->skip) return;
+    __shared__ uint8_t lut[64];
+    __shared__ uint32_t lab[4 * kTC];                          // local labels, index arm * kTC + cell
+    build_incell_lut(lut);
+    __syncthreads();
+    const SwBondCtx k = sw_ctx(a);
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+    uint32_t mk[kTC / 256];
+    // 1: bonds of the tile's cells; local labels from the in-cell components
+#pragma unroll
+    for (uint32_t i = 0; i < kTC / 256; ++i) {
+        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        const uint32_t x = x0 + lx, y = y0 + ly;
+        uint32_t m = 0;
+        if (x < L && y < L) m = sw_bond_mask(a, k, x + y * L, x, y);
+        mk[i] = m;
+        const uint32_t l4 = lut[m >> 2];
+        lab[lc] = (l4 & 3) * kTC + lc;
+        lab[kTC + lc] = ((l4 >> 2) & 3) * kTC + lc;
+        lab[2 * kTC + lc] = ((l4 >> 4) & 3) * kTC + lc;
+        lab[3 * kTC + lc] = ((l4 >> 6) & 3) * kTC + lc;
+    }
+    __syncthreads();
+    // 2: covalent links inside the tile
+#pragma unroll
+    for (uint32_t i = 0; i < kTC / 256; ++i) {
+        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        const uint32_t m = mk[i];
+        if ((m & 1) && lx + 1 < kTW && x0 + lx + 1 < L) unite_lds(lab, lc, kTC + lc + 1);
+        if ((m & 2) && ly + 1 < kTH && y0 + ly + 1 < L) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
+    }
+    __syncthreads();
+    // 3: every bond index of the tile points at its tile-local minimum (global index)
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t v = threadIdx.x + 256 * i;
+        const uint32_t lc = v % kTC, lx = lc % kTW, ly = lc / kTW;
+        if (x0 + lx < L && y0 + ly < L) {
+            const uint32_t r = find_root_lds(lab, v);
+            const uint32_t rc = r % kTC;
+            const uint32_t rg = (r / kTC) * N + (y0 + rc / kTW) * L + (x0 + rc % kTW);
+            a.label[(v / kTC) * N + (y0 + ly) * L + (x0 + lx)] = rg;
+        }
+    }
+}
+
+// Covalent links that leave their tile: +x links of the last column of each
+// tile (and of column L-1, which wraps), +y links of the last row of each
+// tile (and of row L-1).  Thread i < L * ncx handles column-edge cells,
+// the rest row-edge cells.
+__global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint32_t ncx, uint32_t ncy)
+{
+    if (a.st->skip) return;
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t nx = ncx * L, ny = ncy * L;
+    if (i < nx) {
+        const uint32_t y = i / ncx, j = i - y * ncx;
+        const uint32_t x = min(j * kTW + kTW - 1, L - 1);     // last column of tile j (clamped: x = L-1)
+        const uint32_t c = x + y * L;
+        if (a.mask[c] & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + y * L);
+    } else if (i < nx + ny) {
+        const uint32_t r = i - nx;
+        const uint32_t x = r / ncy, j = r - x * ncy;
+        const uint32_t y = min(j * kTH + kTH - 1, L - 1);
+        const uint32_t c = x + y * L;
+        if (a.mask[c] & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : y + 1) * L);
     }
 }
 
