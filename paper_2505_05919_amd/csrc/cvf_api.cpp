@@ -342,6 +342,8 @@ int cvf_labels(cvf_state* st, uint32_t* d_out, void* stream)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return CVF_EHIP;
     if (!done) return CVF_ESTATE;
+    e = launch_sw_flatten(st->la, s);
+    if (e != hipSuccess) return CVF_EHIP;
     return hip_status(hipMemcpyAsync(d_out, st->label, 4ull * st->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
 }
 

@@ -121,6 +121,7 @@ hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_flatten(const LatticeArgs& a, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,
 // count+1 prefix sums of workgroups); all chains share q.
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,

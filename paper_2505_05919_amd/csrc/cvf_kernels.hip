@@ -223,6 +223,17 @@ __global__ __launch_bounds__(64) void volume_kernel(VolArgs a)
 
 #include "met_sweep.h"
 
+// Raw buffer helpers for the recount (the sweep kernels have their own).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(uint8_t* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t ld8b(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
+
 #include "sw_step.h"
 
 __global__ void obs_zero_kernel(DevObs* o)
@@ -325,6 +336,16 @@ hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
                           hipStream_t s)
 {
+    if (!with_counts) {
+        // rows per wavefront for ~8192 wavefronts
+        const uint32_t groups = (a.L / 2 + 63) / 64;
+        const uint32_t wpg = groups >= 8192 ? 1 : 8192 / groups;
+        const uint32_t rows = (a.L + wpg - 1) / wpg;
+        const uint32_t segs = (a.L + rows - 1) / rows;
+        const dim3 grid(groups, (segs + 3) / 4);
+        recount_rows_kernel<<<grid, 256, 0, s>>>(a, out, spread, step_gate, rows);
+        return hipGetLastError();
+    }
     recount_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a, out, spread, with_counts, step_gate);
     return hipGetLastError();
 }
@@ -405,6 +426,12 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint3
     case 2: sw_batch_kernel<2><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
     default: sw_batch_kernel<3><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sw_flatten(const LatticeArgs& a, hipStream_t s)
+{
+    sw_flatten_kernel<<<grid_for(4ull * a.N), kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

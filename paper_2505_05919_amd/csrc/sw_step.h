@@ -25,6 +25,44 @@ __device__ __forceinline__ void recount_cell(const LatticeArgs& a, uint32_t c, u
     }
 }
 
+// Row-based recount (any even L): lane i owns the cells 2i, 2i+1 of the rows
+// of its wavefront; 16-bit loads of the four planes, wave-uniform row offsets.
+__device__ __forceinline__ uint32_t ld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+
+__global__ __launch_bounds__(256) void recount_rows_kernel(LatticeArgs a, int64_t* out, int spread, int step_gate,
+                                                           uint32_t rows)
+{
+    if (step_gate && a.st->skip) return;
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t pair = blockIdx.x * 64 + lane;
+    const uint32_t y0 = (blockIdx.y * 4 + wave) * rows;
+    int hb = 0, co = 0;
+    if (pair < (L >> 1) && y0 < L) {
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.sigma, 4 * N);
+        const uint32_t x = 2 * pair, xn = (x + 2 == L) ? 0 : x + 2;
+        const uint32_t y1 = min(y0 + rows, L);
+        for (uint32_t y = y0; y < y1; ++y) {
+            const uint32_t o = y * L, op = ((y + 1 == L) ? 0 : y + 1) * L;
+            const uint32_t d0 = ld16(rs, x, o), d1 = ld16(rs, x, o + N), d2 = ld16(rs, x, o + 2 * N),
+                           d3 = ld16(rs, x, o + 3 * N);
+            const uint32_t u3 = ld16(rs, x, 3 * N + op);           // arm 3 of the row above
+            const uint32_t n1 = ld8b(rs, xn, o + N);                // arm 1 of the cell right of the pair
+            const uint32_t a0 = d0 & 255, b0 = d0 >> 8, a1 = d1 & 255, b1 = d1 >> 8;
+            const uint32_t a2 = d2 & 255, b2 = d2 >> 8, a3 = d3 & 255, b3 = d3 >> 8;
+            hb += (a0 == b1) + (b0 == n1) + (a2 == (u3 & 255)) + (b2 == (u3 >> 8));
+            co += (a0 == a1) + (a0 == a2) + (a0 == a3) + (a1 == a2) + (a1 == a3) + (a2 == a3);
+            co += (b0 == b1) + (b0 == b2) + (b0 == b3) + (b1 == b2) + (b1 == b3) + (b2 == b3);
+        }
+    }
+    const int v[2] = {hb, co};
+    block_add<2>(v, out + ((blockIdx.x + blockIdx.y * gridDim.x) & (spread - 1)), spread);
+}
+
 __global__ __launch_bounds__(kBlock) void recount_kernel(LatticeArgs a, int64_t* out, int spread, int with_counts,
                                                          int step_gate)
 {
@@ -317,8 +355,9 @@ __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint
     }
 }
 
-// Flatten the labels of cell c to their roots (the cluster minima) and shift
-// sigma by the cluster's r = pick(w0 of Philox(root, t, 0, SWF), q), NULL -> 0.
+// Shift sigma of cell c by its clusters' r = pick(w0 of Philox(root, t, 0,
+// SWF), q), NULL -> 0; root = the cluster minimum.  The labels themselves are
+// flattened only when they are read out (sw_flatten_kernel).
 __device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, uint32_t c)
 {
     const uint32_t N = a.N;
@@ -327,13 +366,20 @@ __device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, u
     for (int arm = 0; arm < 4; ++arm) {
         const uint32_t idx = arm * N + c;
         const uint32_t r = find_root(a.label, idx);
-        a.label[idx] = r;
         const uint32_t w = philox(r, t, 0u, kStreamSwf, a.key0, a.key1).x;
         const int k = (w <= a.flip_lim) ? (int)((double)w * a.flip_invd) : 0;
         int sv = a.sigma[idx] + k;
         sv = sv >= q ? sv - q : sv;
         a.sigma[idx] = (uint8_t)sv;
     }
+}
+
+// Point every label at its root (the minimum of its cluster).
+__global__ __launch_bounds__(kBlock) void sw_flatten_kernel(LatticeArgs a)
+{
+    const uint32_t V = 4 * a.N;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < V; i += gridDim.x * kBlock)
+        a.label[i] = find_root(a.label, i);
 }
 
 __global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
