@@ -115,11 +115,9 @@ hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int wi
 hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
 hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
                             double Jsigma, double P, double vHB, hipStream_t s);
-hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s);
 // Tiled SW labelling: bonds + in-tile unions, then the tile-crossing links.
 hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_flatten(const LatticeArgs& a, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,

@@ -133,86 +133,96 @@ __global__ __launch_bounds__(kBlock) void sigma_init_kernel(LatticeArgs a)
 // same order as the sequential definition.
 // ---------------------------------------------------------------------------
 // Executed by one full wavefront (lanes 0..63); `term` is 40 doubles of LDS.
+// Every global load is issued before the first store, so the whole move
+// costs one memory round trip.
 __device__ void volume_step(const VolArgs& a, double* term)
 {
     const int lane = threadIdx.x & 63;
-    int64_t hb = 0, co = 0, ac = 0;
-    for (int i = lane; i < kSlots; i += 64) {
-        hb += a.slots[i];
-        co += a.slots[kSlots + i];
-        ac += a.slots[2 * kSlots + i];
-        a.slots[i] = 0;
-        a.slots[kSlots + i] = 0;
-        a.slots[2 * kSlots + i] = 0;
-    }
-    hb = wave_sum64(hb);
-    co = wave_sum64(co);
-    ac = wave_sum64(ac);
     DevState* st = a.st;
-    if (a.mode == kVolFold) {
+    int64_t sl[3][kSlots / 64];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) sl[j][k] = a.slots[j * kSlots + k * 64 + lane];
+    const int64_t t_next = st->t_next, stop_at = st->stop_at;
+    const int64_t hb0 = st->n_hb_raw, co0 = st->n_coop, macc0 = st->met_acc, matt0 = st->met_att;
+    const int64_t vatt0 = st->vol_att, vacc0 = st->vol_acc;
+    const double v0 = st->v, u0 = st->u;
+    const int th0 = st->theta;
+    const double r2 = lane < 40 ? a.tab->r2[lane] : 0.0;
+    int64_t hb = 0, co = 0, ac = 0;
+#pragma unroll
+    for (int k = 0; k < kSlots / 64; ++k) {
+        hb += sl[0][k];
+        co += sl[1][k];
+        ac += sl[2][k];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
+    const int64_t n_hb = hb0 + wave_sum64(hb);
+    const int64_t n_co = co0 + wave_sum64(co);
+    const int64_t m_acc = macc0 + wave_sum64(ac);
+    if (a.mode == kVolFold || t_next >= stop_at) {   // fold only; at the step limit the step kernels skip
         if (lane == 0) {
-            st->n_hb_raw += hb;
-            st->n_coop += co;
-            st->met_acc += ac;
+            st->n_hb_raw = n_hb;
+            st->n_coop = n_co;
+            st->met_acc = m_acc;
+            if (a.mode != kVolFold) st->skip = 1;
         }
         return;
     }
-    if (st->t_next >= st->stop_at) {          // step limit: fold only, the step kernels skip
-        if (lane == 0) {
-            st->n_hb_raw += hb;
-            st->n_coop += co;
-            st->met_acc += ac;
-            st->skip = 1;
-        }
-        return;
-    }
-    const uint32_t t = (uint32_t)st->t_next;
+    const uint32_t t = (uint32_t)t_next;
     const uint4 w = philox(0u, t, 0u, kStreamVol, a.key0, a.key1);
     const double u = (double)((int64_t)2 * (int64_t)w.x + 1 - 4294967296LL) * (1.0 / 4294967296.0);
-    const double v0 = st->v;
     const double v1 = v0 + a.dv_max * u;
     const bool inside = a.do_volume && v1 >= 1.0;
     if (inside && lane >= 1 && lane <= 36) {
         const double d2 = v1 * (double)lane;
         const double s6 = 1.0 / (d2 * d2 * d2);
-        term[lane] = a.tab->r2[lane] * (s6 * s6 - s6);
+        term[lane] = r2 * (s6 * s6 - s6);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (lane != 0) return;
-    st->skip = 0;
-    st->n_hb_raw += hb;
-    st->n_coop += co;
-    st->met_acc += ac;
-    st->t_cur = t;
-    st->t_next += 1;
-    st->met_att += a.met_att_add;
+    double v = v0, uu = u0;
+    int th = th0;
+    int64_t vatt = vatt0, vacc = vacc0;
     if (a.do_volume) {
-        st->vol_att += 1;
+        vatt += 1;
         if (inside) {
             double sum = 0.0;
             for (int m = 1; v1 * (double)m <= 36.0; ++m) sum = sum + term[m];
             const double u1 = 2.0 * sum;
-            const int th0 = st->theta;
             const int th1 = v1 < 2.0 ? 1 : 0;
-            const double dH = (a.Nd * (u1 - st->u))
+            const double dH = (a.Nd * (u1 - u0))
                             + ((a.P * a.Nd) * (v1 - v0))
-                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)st->n_hb_raw);
+                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)n_hb);
             bool acc = dH <= 0.0;
             if (!acc) acc = ((double)w.y + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
             if (acc) {
-                st->v = v1;
-                st->u = u1;
-                st->theta = th1;
-                st->vol_acc += 1;
+                v = v1;
+                uu = u1;
+                th = th1;
+                vacc += 1;
             }
         }
     }
-    if (a.mode == kVolSw) {         // the SW step ends with a full recount
-        st->n_hb_raw = 0;
-        st->n_coop = 0;
-    }
+    st->skip = 0;
+    st->t_cur = t;
+    st->t_next = t_next + 1;
+    st->met_att = matt0 + a.met_att_add;
+    st->met_acc = m_acc;
+    st->vol_att = vatt;
+    st->vol_acc = vacc;
+    st->v = v;
+    st->u = uu;
+    st->theta = th;
+    const bool sw = a.mode == kVolSw;            // the SW step ends with a full recount
+    st->n_hb_raw = sw ? 0 : n_hb;
+    st->n_coop = sw ? 0 : n_co;
 }
 
 __global__ __launch_bounds__(64) void volume_kernel(VolArgs a)
@@ -375,18 +385,6 @@ hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s)
     const uint32_t ncx = (a.L + kTW - 1) / kTW, ncy = (a.L + kTH - 1) / kTH;
     const uint64_t n = (uint64_t)(ncx + ncy) * a.L;
     sw_union_edges_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, ncx, ncy);
-    return hipGetLastError();
-}
-
-hipError_t launch_sw_bonds(const LatticeArgs& a, hipStream_t s)
-{
-    sw_bonds_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_sw_union(const LatticeArgs& a, hipStream_t s)
-{
-    sw_union_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

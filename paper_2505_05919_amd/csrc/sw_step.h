@@ -175,21 +175,6 @@ __device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBond
     a.label[3 * N + c] = ((l4 >> 6) & 3) * (uint32_t)N + c;
 }
 
-__global__ __launch_bounds__(kBlock) void sw_bonds_kernel(LatticeArgs a)
-{
-    if (a.st->skip) return;
-    __shared__ uint8_t lut[64];
-    build_incell_lut(lut);
-    __syncthreads();
-    const SwBondCtx k = sw_ctx(a);
-    const double inv_L = 1.0 / (double)a.L;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
-        uint32_t x;
-        const uint32_t y = divmod(c, a.L, inv_L, x);
-        sw_bonds_cell(a, k, lut, c, x, y);
-    }
-}
-
 // Root of x: follow parents until a self-loop.  label[x] <= x everywhere, so
 // the chain strictly decreases and ends.
 __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
@@ -231,17 +216,6 @@ __device__ __forceinline__ void sw_union_cell(const LatticeArgs& a, uint32_t c, 
     const uint32_t row = y * L;
     if (m & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + row);
     if (m & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : row + L));
-}
-
-__global__ __launch_bounds__(kBlock) void sw_union_kernel(LatticeArgs a)
-{
-    if (a.st->skip) return;
-    const double inv_L = 1.0 / (double)a.L;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) {
-        uint32_t x;
-        const uint32_t y = divmod(c, a.L, inv_L, x);
-        sw_union_cell(a, c, x, y);
-    }
 }
 
 // ---------------------------------------------------------------------------
