@@ -107,8 +107,9 @@ typedef struct cvf_state cvf_state;
 int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
 
 /* Device workspace needed for the algorithms in algo_mask: Metropolis
- * needs a few KB; Swendsen-Wang adds 17 bytes per cell (labels of the 4N
- * bond indices and one bond mask byte per cell).  Host only. */
+ * needs a few KB; Swendsen-Wang adds 25 bytes per cell (uint32 labels and
+ * uint16 tile-local roots of the 4N bond indices, one bond mask byte per
+ * cell) and 80 bytes per 64 x 16-cell tile.  Host only. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
 /* Create a chain.  d_sigma: 4*L*L bytes of device memory, layout above;
@@ -141,9 +142,11 @@ int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
  * *out.  Synchronises stream. */
 int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
 
-/* Copy the cluster labels of the last Swendsen-Wang step (4*L*L uint32,
+/* Write the cluster labels of the last Swendsen-Wang step (4*L*L uint32,
  * label[idx] = smallest flat index in idx's cluster) to device memory
- * d_out.  CVF_ESTATE if no Swendsen-Wang step has run.  Asynchronous. */
+ * d_out, which must not overlap the chain's workspace or sigma.
+ * CVF_ESTATE if no Swendsen-Wang step has run.  Waits for the stream's
+ * earlier work (to read that flag), then enqueues the write. */
 int cvf_labels(cvf_state *st, uint32_t *d_out, void *stream);
 
 /* Step limit: steps with index >= stop_at (counted from 0 at cvf_init) are

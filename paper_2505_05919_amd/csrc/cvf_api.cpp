@@ -33,6 +33,8 @@ struct cvf_state {
     DevObs* dobs;
     uint32_t* label;
     uint8_t* mask;
+    uint8_t* edge;
+    uint16_t* lroot;
     DevTables htab;          // host copy (source of the init copy, test hook)
     LatticeArgs la;
     VolArgs va;
@@ -60,7 +62,14 @@ int validate(const cvf_params* p)
     return CVF_OK;
 }
 
-size_t sw_bytes(uint64_t N) { return align256(4 * N * sizeof(uint32_t)) + align256(N); }
+// SW workspace: labels (4N uint32), bond mask (N bytes), tile edge bytes,
+// tile-local roots (4N uint16).
+size_t sw_tiles(uint64_t L) { return ((L + kTW - 1) / kTW) * ((L + kTH - 1) / kTH); }
+size_t sw_bytes(uint64_t L)
+{
+    return align256(4 * L * L * sizeof(uint32_t)) + align256(L * L) + align256(sw_tiles(L) * kEdgeBytes) +
+           align256(4 * L * L * sizeof(uint16_t));
+}
 
 // Number of integer points on the circle i^2 + j^2 = m, counted over the
 // first quadrant (i > 0, j >= 0) and multiplied by the 4 rotations.
@@ -182,9 +191,8 @@ int cvf_workspace_bytes(const cvf_params* p, int algo_mask, size_t* bytes)
     if (!bytes || (algo_mask & ~(CVF_ALGO_METROPOLIS | CVF_ALGO_SW))) return CVF_EINVAL;
     int rc = validate(p);
     if (rc) return rc;
-    const uint64_t N = (uint64_t)p->L * (uint64_t)p->L;
     size_t b = kBaseBytes;
-    if (algo_mask & CVF_ALGO_SW) b += sw_bytes(N);
+    if (algo_mask & CVF_ALGO_SW) b += sw_bytes((uint64_t)p->L);
     *bytes = b;
     return CVF_OK;
 }
@@ -205,13 +213,15 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     st->work = (char*)d_work;
     st->work_bytes = work_bytes;
     st->N = (uint32_t)p->L * (uint32_t)p->L;
-    st->has_sw = work_bytes >= kBaseBytes + sw_bytes(st->N);
+    st->has_sw = work_bytes >= kBaseBytes + sw_bytes((uint64_t)p->L);
     st->dst = (DevState*)(st->work + kOffState);
     st->slots = (int64_t*)(st->work + kOffSlots);
     st->dtab = (DevTables*)(st->work + kOffTables);
     st->dobs = (DevObs*)(st->work + kOffObs);
     st->label = st->has_sw ? (uint32_t*)(st->work + kBaseBytes) : nullptr;
     st->mask = st->has_sw ? (uint8_t*)(st->work + kBaseBytes + align256(4ull * st->N * sizeof(uint32_t))) : nullptr;
+    st->edge = st->has_sw ? st->mask + align256(st->N) : nullptr;
+    st->lroot = st->has_sw ? (uint16_t*)(st->edge + align256(sw_tiles((uint64_t)p->L) * kEdgeBytes)) : nullptr;
     build_tables(p, &st->htab);
 
     const double Jeff = p->J - p->P * p->vHB;
@@ -224,6 +234,8 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     a.tab = st->dtab;
     a.label = st->label;
     a.mask = st->mask;
+    a.edge = st->edge;
+    a.lroot = st->lroot;
     a.L = (uint32_t)p->L;
     a.N = st->N;
     a.key0 = (uint32_t)p->seed;
@@ -306,8 +318,7 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
         TIMED(CVF_K_VOLUME, launch_volume(v, s));
         TIMED(CVF_K_SW_BONDS, launch_sw_tiles(st->la, s));
         TIMED(CVF_K_SW_UNION, launch_sw_union_edges(st->la, s));
-        TIMED(CVF_K_SW_FLIP, launch_sw_flip(st->la, s));
-        TIMED(CVF_K_RECOUNT, launch_recount(st->la, st->slots, kSlots, 0, 1, s));
+        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, s));
     }
     return CVF_OK;
 }
@@ -342,9 +353,7 @@ int cvf_labels(cvf_state* st, uint32_t* d_out, void* stream)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return CVF_EHIP;
     if (!done) return CVF_ESTATE;
-    e = launch_sw_flatten(st->la, s);
-    if (e != hipSuccess) return CVF_EHIP;
-    return hip_status(hipMemcpyAsync(d_out, st->label, 4ull * st->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    return hip_status(launch_sw_labels(st->la, d_out, s));
 }
 
 int cvf_set_stop(cvf_state* st, int64_t stop_at, void* stream)

@@ -19,6 +19,13 @@ constexpr uint32_t kStreamSwf = 4;    // Swendsen-Wang cluster shift
 // same-address atomics do not serialise; the volume kernel folds them.
 constexpr int kSlots = 256;
 
+// Swendsen-Wang tiles: kTW x kTH cells per workgroup (the last tile of a row
+// or column is ragged).  Per tile the bond kernel keeps, for the step's
+// fused recount, the old sigma of the facing arm across the right edge (kTH
+// bytes, one per row) and across the bottom edge (kTW bytes, one per column).
+constexpr uint32_t kTW = 64, kTH = 16, kTC = kTW * kTH;
+constexpr uint32_t kEdgeBytes = kTW + kTH;
+
 // Mutable per-chain scalars, at offset 0 of the workspace.
 struct DevState {
     int64_t t_next;          // index of the next MC step
@@ -67,6 +74,8 @@ struct LatticeArgs {
     const DevTables* tab;
     uint32_t* label;         // Swendsen-Wang only
     uint8_t* mask;           // Swendsen-Wang only
+    uint8_t* edge;           // Swendsen-Wang only: kEdgeBytes per tile
+    uint16_t* lroot;         // Swendsen-Wang only: tile-local root of every bond index (| border flag)
     uint32_t L, N;           // side, L*L
     uint32_t key0, key1;     // Philox key (seed)
     uint32_t q;
@@ -115,11 +124,12 @@ hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int wi
 hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
 hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
                             double Jsigma, double P, double vHB, hipStream_t s);
-// Tiled SW labelling: bonds + in-tile unions, then the tile-crossing links.
+// Tiled SW step: bonds + in-tile unions, the tile-crossing links, then the
+// cluster shift fused with the recount.  Labels are written out on request.
 hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_flatten(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,
 // count+1 prefix sums of workgroups); all chains share q.
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,

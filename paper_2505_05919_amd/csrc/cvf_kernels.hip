@@ -427,15 +427,17 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_sw_flatten(const LatticeArgs& a, hipStream_t s)
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s)
 {
-    sw_flatten_kernel<<<grid_for(4ull * a.N), kBlock, 0, s>>>(a);
+    const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
+    sw_flip_tile_kernel<<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_sw_flip(const LatticeArgs& a, hipStream_t s)
+hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s)
 {
-    sw_flip_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a);
+    const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
+    sw_labels_kernel<<<grid, 256, 0, s>>>(a, out);
     return hipGetLastError();
 }
 

@@ -130,8 +130,9 @@ __device__ __forceinline__ SwBondCtx sw_ctx(const LatticeArgs& a)
 }
 
 // Bond activation of cell c: the 8-bit link mask (also stored in mask[c]).
+// f0o, f2o: the (old) sigma of the arms facing arm 0 and arm 2 of c.
 __device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwBondCtx& k, uint32_t c, uint32_t x,
-                                                 uint32_t y)
+                                                 uint32_t y, int& f0o, int& f2o)
 {
     const uint32_t L = a.L;
     const size_t N = a.N;
@@ -158,6 +159,8 @@ __device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwB
     m |= (s1 == s3 && below(w1.z, k.thr_s)) ? 64u : 0u;
     m |= (s2 == s3 && below(w1.w, k.thr_s)) ? 128u : 0u;
     a.mask[c] = (uint8_t)m;
+    f0o = f0;
+    f2o = f2;
     return m;
 }
 
@@ -167,7 +170,8 @@ __device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBond
                                               uint32_t c, uint32_t x, uint32_t y)
 {
     const size_t N = a.N;
-    const uint32_t m = sw_bond_mask(a, k, c, x, y);
+    int f0, f2;
+    const uint32_t m = sw_bond_mask(a, k, c, x, y, f0, f2);
     const uint32_t l4 = lut[m >> 2];
     a.label[c] = (l4 & 3) * (uint32_t)N + c;
     a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
@@ -219,22 +223,87 @@ __device__ __forceinline__ void sw_union_cell(const LatticeArgs& a, uint32_t c, 
 }
 
 // ---------------------------------------------------------------------------
-// Tiled bond activation + local labelling.  A workgroup owns a tile of
-// kTW x kTH cells: it activates the bonds of every cell of the tile (same
-// decisions as sw_bonds_cell), unites the covalent links that stay inside the
-// tile in LDS (lock-free, ds_min atomics on local indices, whose order is
-// the order of the global flat indices), and writes for every bond index the
-// global index of its tile-local component minimum.  Links that cross a tile
-// edge (or the periodic wrap) are left to sw_union_edges_kernel.
+// Tiled Swendsen-Wang step.  A workgroup owns a tile of kTW x kTH cells, i.e.
+// 4 kTC bond indices with local index v = arm * kTC + ly * kTW + lx, whose
+// order is the order of the global flat indices arm * N + y * L + x.
+//  sw_tile_kernel         bonds of the tile's cells (mask) and the in-tile
+//                         unions in LDS; global labels only where the
+//                         tile-crossing links can reach them: border bond
+//                         indices (-> their tile root) and the roots of the
+//                         components holding one (-> themselves); the old
+//                         sigma facing the right and bottom edges; every
+//                         bond index's tile-local root (uint16, with the
+//                         border flag of its component).
+//  sw_union_edges_kernel  the tile-crossing links (global union-find).
+//  sw_flip_tile_kernel    one shift per tile-local component (its cluster
+//                         minimum comes from the global labels if the
+//                         component touches the border, else it is the
+//                         component's own minimum), shifts sigma and
+//                         recounts N_HB_raw and N_sigma of the new
+//                         configuration.
+//  sw_labels_kernel       the full label array, on request.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kTW = 64, kTH = 16, kTC = kTW * kTH;       // tile: 1024 cells, 4096 bond indices
+constexpr uint32_t kIdx = 0x0FFFu;     // local index bits of an LDS label
+constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
+
+struct TileGeom {
+    uint32_t x0, y0, w, h, id;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(uint32_t L)
+{
+    TileGeom g;
+    g.x0 = blockIdx.x * kTW;
+    g.y0 = blockIdx.y * kTH;
+    g.w = min(kTW, L - g.x0);
+    g.h = min(kTH, L - g.y0);
+    g.id = blockIdx.x + blockIdx.y * gridDim.x;
+    return g;
+}
+
+__device__ __forceinline__ bool tile_in(const TileGeom& g, uint32_t v)
+{
+    const uint32_t lc = v % kTC;
+    return lc % kTW < g.w && lc / kTW < g.h;
+}
+
+__device__ __forceinline__ uint32_t tile_global(const TileGeom& g, uint32_t L, uint32_t N, uint32_t v)
+{
+    const uint32_t lc = v % kTC;
+    return (v / kTC) * N + (g.y0 + lc / kTW) * L + g.x0 + lc % kTW;
+}
+
+// The 4 kTC / 256 = 16 bond indices of a thread: entry i lies in plane i / 4,
+// tile row wave + 4 (i % 4) (wave-uniform) and tile column lane.
+__device__ __forceinline__ uint32_t ent_row(uint32_t wave, uint32_t i) { return wave + 4 * (i & 3); }
+__device__ __forceinline__ uint32_t ent_local(uint32_t wave, uint32_t lane, uint32_t i)
+{
+    return (i >> 2) * kTC + ent_row(wave, i) * kTW + lane;
+}
+
+// The border bond indices of a tile -- the ends of tile-crossing covalent
+// links -- numbered b < 2 kTH + 2 kTW: arm 0 in the last column and arm 1 in
+// the first column (row b), arm 2 in the last row and arm 3 in the first row
+// (column b); 4 kTC if b names no bond index of a ragged tile.
+__device__ __forceinline__ uint32_t border_local(const TileGeom& g, uint32_t b)
+{
+    if (b < kTH) return b < g.h ? b * kTW + g.w - 1 : 4 * kTC;
+    if (b < 2 * kTH) return b - kTH < g.h ? kTC + (b - kTH) * kTW : 4 * kTC;
+    if (b < 2 * kTH + kTW) return b - 2 * kTH < g.w ? 2 * kTC + (g.h - 1) * kTW + (b - 2 * kTH) : 4 * kTC;
+    return b - 2 * kTH - kTW < g.w ? 3 * kTC + (b - 2 * kTH - kTW) : 4 * kTC;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
 
 __device__ __forceinline__ uint32_t find_root_lds(const uint32_t* lab, uint32_t x)
 {
-    uint32_t p = lab[x];
+    uint32_t p = lab[x] & kIdx;
     while (p != x) {
         x = p;
-        p = lab[x];
+        p = lab[x] & kIdx;
     }
     return x;
 }
@@ -256,52 +325,98 @@ __device__ __forceinline__ void unite_lds(uint32_t* lab, uint32_t a, uint32_t b)
     }
 }
 
-__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+// In-tile components from the link masks mk[i] of cells lc = tid + 256 i:
+// the in-cell components (LUT), then the covalent links inside the tile;
+// finally the roots of components holding a border bond index get kBorder.
+// The minimum-index root does not depend on the order of the unions, so
+// every kernel that rebuilds the components from the same mask gets the
+// same roots.  Expects lut ready; ends with a barrier.
+__device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_t (&mk)[kTC / 256], const TileGeom& g)
 {
-    if (a.st->skip) return;
-    __shared__ uint8_t lut[64];
-    __shared__ uint32_t lab[4 * kTC];                          // local labels, index arm * kTC + cell
-    build_incell_lut(lut);
-    __syncthreads();
-    const SwBondCtx k = sw_ctx(a);
-    const uint32_t L = a.L, N = a.N;
-    const uint32_t x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
-    uint32_t mk[kTC / 256];
-    // 1: bonds of the tile's cells; local labels from the in-cell components
 #pragma unroll
     for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
-        const uint32_t x = x0 + lx, y = y0 + ly;
-        uint32_t m = 0;
-        if (x < L && y < L) m = sw_bond_mask(a, k, x + y * L, x, y);
-        mk[i] = m;
-        const uint32_t l4 = lut[m >> 2];
+        const uint32_t lc = threadIdx.x + 256 * i;
+        const uint32_t l4 = lut[mk[i] >> 2];
         lab[lc] = (l4 & 3) * kTC + lc;
         lab[kTC + lc] = ((l4 >> 2) & 3) * kTC + lc;
         lab[2 * kTC + lc] = ((l4 >> 4) & 3) * kTC + lc;
         lab[3 * kTC + lc] = ((l4 >> 6) & 3) * kTC + lc;
     }
     __syncthreads();
-    // 2: covalent links inside the tile
 #pragma unroll
     for (uint32_t i = 0; i < kTC / 256; ++i) {
         const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
         const uint32_t m = mk[i];
-        if ((m & 1) && lx + 1 < kTW && x0 + lx + 1 < L) unite_lds(lab, lc, kTC + lc + 1);
-        if ((m & 2) && ly + 1 < kTH && y0 + ly + 1 < L) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
+        if ((m & 1) && lx + 1 < g.w) unite_lds(lab, lc, kTC + lc + 1);
+        if ((m & 2) && ly + 1 < g.h) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
     }
     __syncthreads();
-    // 3: every bond index of the tile points at its tile-local minimum (global index)
+    if (threadIdx.x < 2 * (kTW + kTH)) {
+        const uint32_t v = border_local(g, threadIdx.x);
+        if (v < 4 * kTC) atomicOr(lab + find_root_lds(lab, v), kBorder);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom& g, uint32_t (&mk)[kTC / 256])
+{
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
-        const uint32_t v = threadIdx.x + 256 * i;
-        const uint32_t lc = v % kTC, lx = lc % kTW, ly = lc / kTW;
-        if (x0 + lx < L && y0 + ly < L) {
-            const uint32_t r = find_root_lds(lab, v);
-            const uint32_t rc = r % kTC;
-            const uint32_t rg = (r / kTC) * N + (y0 + rc / kTW) * L + (x0 + rc % kTW);
-            a.label[(v / kTC) * N + (y0 + ly) * L + (x0 + lx)] = rg;
+    for (uint32_t i = 0; i < kTC / 256; ++i) {
+        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        mk[i] = (lx < g.w && ly < g.h) ? a.mask[(g.y0 + ly) * a.L + g.x0 + lx] : 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+{
+    if (a.st->skip) return;
+    __shared__ uint8_t lut[64];
+    __shared__ uint32_t lab[4 * kTC];
+    build_incell_lut(lut);
+    const SwBondCtx k = sw_ctx(a);
+    const uint32_t L = a.L, N = a.N;
+    const TileGeom g = tile_geom(L);
+    uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
+    uint32_t mk[kTC / 256];
+#pragma unroll
+    for (uint32_t i = 0; i < kTC / 256; ++i) {
+        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        uint32_t m = 0;
+        if (lx < g.w && ly < g.h) {
+            const uint32_t x = g.x0 + lx, y = g.y0 + ly;
+            int f0, f2;
+            m = sw_bond_mask(a, k, x + y * L, x, y, f0, f2);
+            if (lx == g.w - 1) edge[ly] = (uint8_t)f0;
+            if (ly == g.h - 1) edge[kTH + lx] = (uint8_t)f2;
         }
+        mk[i] = m;
+    }
+    __syncthreads();
+    tile_components(lab, lut, mk, g);
+    // every bond index: its tile-local root (| flag); flagged roots: a
+    // global self-label; border bond indices: a global label of their root
+    const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool col_in = lane < g.w;
+    const uint32_t voff = col_in ? 2 * (g.x0 + lane) : 0u;
+#pragma unroll
+    for (uint32_t p = 0; p < 4; ++p) {
+        const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
+#pragma unroll 2
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t ly = wave + 4 * k;
+            if (ly >= g.h) break;
+            const uint32_t v = p * kTC + ly * kTW + lane;
+            const uint32_t r = find_root_lds(lab, v);
+            const uint32_t flag = lab[r] & kBorder;
+            if (col_in) {
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(r | flag), rl, (int)voff, (int)(2 * (g.y0 + ly) * L), 0);
+                if (r == v && flag) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, v);
+            }
+        }
+    }
+    if (threadIdx.x < 2 * (kTW + kTH)) {
+        const uint32_t v = border_local(g, threadIdx.x);
+        if (v < 4 * kTC) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, find_root_lds(lab, v));
     }
 }
 
@@ -348,20 +463,174 @@ __device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, u
     }
 }
 
-// Point every label at its root (the minimum of its cluster).
-__global__ __launch_bounds__(kBlock) void sw_flatten_kernel(LatticeArgs a)
-{
-    const uint32_t V = 4 * a.N;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < V; i += gridDim.x * kBlock)
-        a.label[i] = find_root(a.label, i);
-}
-
-__global__ __launch_bounds__(kBlock) void sw_flip_kernel(LatticeArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
 {
     if (a.st->skip) return;
+    __shared__ uint16_t roots[4 * kTC];      // component roots (| kBorder), compacted; then the new sigma
+    __shared__ uint8_t sh[4 * kTC];          // shift of each component root
+    __shared__ uint8_t across[kEdgeBytes];   // new sigma facing the right / bottom edge
+    __shared__ uint32_t nroot;
+    uint8_t* nsg = reinterpret_cast<uint8_t*>(roots);
+    if (threadIdx.x == 0) nroot = 0;
+    const uint32_t L = a.L, N = a.N, q = a.q;
+    const TileGeom g = tile_geom(L);
     const uint32_t t = a.st->t_cur;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->sw_done = 1;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < a.N; c += gridDim.x * kBlock) sw_flip_cell(a, t, c);
+    if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
+    // entry i: plane i / 4, tile row wave + 4 (i % 4), column lane
+    const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool col_in = lane < g.w;
+    const uint32_t voff = col_in ? g.x0 + lane : 0u;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N);
+    uint32_t os[4 * kTC / 256], lr[4 * kTC / 256];     // old sigma, local root | kBorder
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t p = i >> 2, ly = ent_row(wave, i);
+        os[i] = 0;
+        lr[i] = ent_local(wave, lane, i);
+        if (ly < g.h) {
+            const uint32_t row = (g.y0 + ly) * L;
+            os[i] = __builtin_amdgcn_raw_buffer_load_b8(rs, (int)voff, (int)(p * N + row), 0);
+            const uint32_t l = __builtin_amdgcn_raw_buffer_load_b16(buf_rsrc(a.lroot + (size_t)p * N, 2 * N),
+                                                                   (int)(2 * voff), (int)(2 * row), 0);
+            if (col_in) lr[i] = l;
+        }
+    }
+    // component roots, compacted: one LDS atomic per wavefront
+    uint64_t bal[4 * kTC / 256];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t v = ent_local(wave, lane, i);
+        bal[i] = __ballot(col_in && ent_row(wave, i) < g.h && (lr[i] & kIdx) == v);
+        cnt += (uint32_t)__popcll(bal[i]);
+    }
+    __syncthreads();                          // nroot = 0
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&nroot, cnt);
+    base = (uint32_t)__shfl((int)base, 0);
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t pos =
+            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i], 0u));
+        if ((bal[i] >> lane) & 1) roots[pos] = (uint16_t)lr[i];
+        base += (uint32_t)__popcll(bal[i]);
+    }
+    __syncthreads();
+    // Jobs: one shift per component root, then the facing arms across the
+    // right edge (rows p < kTH) and the bottom edge (columns p - kTH).  Four
+    // jobs per thread at a time, their root chains followed in lockstep.
+    const uint32_t nr = nroot, njobs = nr + kEdgeBytes;
+    const uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
+    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += 4 * 256) {
+        uint32_t x[4], dst[4];
+        bool chase[4], live[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = j0 + 256 * k;
+            live[k] = j < njobs;
+            chase[k] = false;
+            x[k] = 0;
+            dst[k] = 0;
+            if (j < nr) {
+                const uint32_t e = roots[j];
+                dst[k] = e & kIdx;
+                x[k] = tile_global(g, L, N, e & kIdx);
+                chase[k] = (e & kBorder) != 0;
+            } else if (live[k]) {
+                const uint32_t p = j - nr;
+                dst[k] = 0x10000u | p;
+                if (p < kTH) {
+                    live[k] = p < g.h;
+                    const uint32_t xx = g.x0 + g.w - 1, yy = g.y0 + p;
+                    x[k] = N + ((xx + 1 == L) ? 0 : xx + 1) + yy * L;
+                } else {
+                    live[k] = p - kTH < g.w;
+                    const uint32_t xx = g.x0 + (p - kTH), yy = g.y0 + g.h - 1;
+                    x[k] = 3 * N + xx + ((yy + 1 == L) ? 0 : yy + 1) * L;
+                }
+                chase[k] = live[k];
+                if (!live[k]) x[k] = 0;
+            }
+        }
+        while (chase[0] || chase[1] || chase[2] || chase[3]) {
+            uint32_t pn[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pn[k] = a.label[chase[k] ? x[k] : 0u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (chase[k]) {
+                    if (pn[k] == x[k]) chase[k] = false;
+                    else x[k] = pn[k];
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!live[k]) continue;
+            const uint32_t w = philox(x[k], t, 0u, kStreamSwf, a.key0, a.key1).x;
+            const uint32_t sft = (w <= a.flip_lim) ? (uint32_t)((double)w * a.flip_invd) : 0u;
+            if (dst[k] < 0x10000u) {
+                sh[dst[k]] = (uint8_t)sft;
+            } else {
+                const uint32_t p = dst[k] & 0xFFFFu;
+                const uint32_t s = edge[p] + sft;
+                across[p] = (uint8_t)(s >= q ? s - q : s);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t ly = ent_row(wave, i);
+        uint32_t s = os[i] + sh[lr[i] & kIdx];
+        s = s >= q ? s - q : s;
+        if (col_in && ly < g.h)
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)s, rs, (int)voff, (int)((i >> 2) * N + (g.y0 + ly) * L), 0);
+        os[i] = s;
+    }
+    __syncthreads();                          // the root list is dead: its space holds the new sigma
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) nsg[ent_local(wave, lane, i)] = (uint8_t)os[i];
+    __syncthreads();
+    // recount of the new configuration: the +x and +y HB pairs and the six
+    // in-cell pairs of every cell of the tile
+    int hb = 0, co = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kTC / 256; ++i) {
+        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        if (lx < g.w && ly < g.h) {
+            const uint32_t s0 = nsg[lc], s1 = nsg[kTC + lc], s2 = nsg[2 * kTC + lc], s3 = nsg[3 * kTC + lc];
+            const uint32_t f0 = lx + 1 < g.w ? nsg[kTC + lc + 1] : across[ly];
+            const uint32_t f2 = ly + 1 < g.h ? nsg[3 * kTC + lc + kTW] : across[kTH + lx];
+            hb += (s0 == f0) + (s2 == f2);
+            co += (s0 == s1) + (s0 == s2) + (s0 == s3) + (s1 == s2) + (s1 == s3) + (s2 == s3);
+        }
+    }
+    const int v2[2] = {hb, co};
+    block_add<2>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
+}
+
+// label[idx] = the minimum of idx's cluster, for every bond index; written
+// to out (4N uint32).  Works from the mask and the global labels left by
+// either the tiled or the batched step.
+__global__ __launch_bounds__(256) void sw_labels_kernel(LatticeArgs a, uint32_t* __restrict__ out)
+{
+    __shared__ uint8_t lut[64];
+    __shared__ uint32_t lab[4 * kTC];
+    build_incell_lut(lut);
+    const uint32_t L = a.L, N = a.N;
+    const TileGeom g = tile_geom(L);
+    uint32_t mk[kTC / 256];
+    tile_masks(a, g, mk);
+    __syncthreads();
+    tile_components(lab, lut, mk, g);
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const uint32_t v = threadIdx.x + 256 * i;
+        if (!tile_in(g, v)) continue;
+        const uint32_t r = find_root_lds(lab, v);
+        const uint32_t gr = tile_global(g, L, N, r);
+        out[tile_global(g, L, N, v)] = (lab[r] & kBorder) ? find_root(a.label, gr) : gr;
+    }
 }
 
 // ---------------------------------------------------------------------------
