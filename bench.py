@@ -29,8 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # full-rate 32-bit VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic integer ops per bond update: half a Philox4x32-10 block (10 rounds x
-# (2 single-instruction 32x32->64 products + 4 XORs) / 2 = 30) + the decision (14)
-ALU_OPS_PER_UPDATE = 44
+# (2 single-instruction 32x32->64 products + 2 three-input XORs) / 2 = 20) + the
+# decision (14)
+ALU_OPS_PER_UPDATE = 34
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "met_colour_L4096_counters.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "met_sweep.h")]
 

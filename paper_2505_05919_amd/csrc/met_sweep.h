@@ -213,9 +213,8 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
     st32(rs, put2<B1, B2>(q.d3, a3, b3), x4, o0 + 3 * N);
 }
 
-__device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl)
+__device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int theta)
 {
-    const int theta = a.st->theta;
     const int tid = threadIdx.x;
     if (tid < 32) {
         const int dd = tid - 16;                          // dc + 8 dh
@@ -244,26 +243,30 @@ __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32
 }
 
 // One workgroup's share of a colour pass with quad lanes: column group bx
-// (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  Returns the
-// lane's packed counter sum.
+// (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  The first
+// row's loads are issued before the LDS table is built, so both latencies
+// overlap.  Returns the lane's packed counter sum.
 template <int Q, int KAPPA>
-__device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, const uint2* tbl, uint32_t t, uint32_t bx,
-                                                   uint32_t by)
+__device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
+                                                   uint32_t bx, uint32_t by)
 {
     const uint32_t L = a.L;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t j = bx * 64 + lane;
     const uint32_t y0 = (by * 4 + wave) * a.rows;      // even
+    const bool active = j < (L >> 2) && y0 < L;
+    const uint32_t x4 = 4 * j;
+    const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 == L) ? 0 : x4 + 4;
+    const uint32_t y1 = min(y0 + a.rows, L);
+    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
+    // even rows: updated cells at bytes KAPPA, KAPPA+2; odd rows: 1-KAPPA, 3-KAPPA
+    constexpr int PE = KAPPA, PO = 1 - KAPPA;
+    QuadBytes cur = {};
+    if (active) cur = met_load4<PE>(a, rs, y0, x4, xl, xr);
+    met_table(a, tbl, theta);
     uint32_t wsum = 0;
-    if (j < (L >> 2) && y0 < L) {
-        const uint32_t x4 = 4 * j;
-        const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 == L) ? 0 : x4 + 4;
-        const uint32_t y1 = min(y0 + a.rows, L);
-        const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
-        // even rows: updated cells at bytes KAPPA, KAPPA+2; odd rows: 1-KAPPA, 3-KAPPA
-        constexpr int PE = KAPPA, PO = 1 - KAPPA;
-        QuadBytes cur = met_load4<PE>(a, rs, y0, x4, xl, xr);
+    if (active) {
         for (uint32_t y = y0; y < y1; y += 2) {
             const QuadBytes odd = met_load4<PO>(a, rs, y + 1, x4, xl, xr);
             met_quad<Q, PE>(a, rs, tbl, t, y, x4, cur, wsum);
@@ -280,36 +283,40 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, const u
 template <int Q, int KAPPA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_sweep4_kernel(LatticeArgs a)
 {
-    if (a.st->skip) return;                                // step limit reached
+    const int skip = a.st->skip, theta = a.st->theta;
+    const uint32_t t = a.st->t_cur;
+    if (skip) return;                                      // step limit reached
     __shared__ uint2 tbl[32];
-    met_table(a, tbl);
-    const uint32_t wsum = met_quad_block<Q, KAPPA>(a, tbl, a.st->t_cur, blockIdx.x, blockIdx.y);
+    const uint32_t wsum = met_quad_block<Q, KAPPA>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // Byte-lane variant (any even L): lane i owns the column pair (2i, 2i+1).
 template <int Q>
-__device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, const uint2* tbl, uint32_t t, int colour,
-                                                   uint32_t bx, uint32_t by)
+__device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
+                                                   int colour, uint32_t bx, uint32_t by)
 {
     const uint32_t L = a.L, half = L >> 1;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t pair = bx * 64 + lane;
     const uint32_t y0 = (by * 4 + wave) * a.rows;    // even
+    const bool active = pair < half && y0 < L;
+    // column of the updated cell in even rows (A) and odd rows (B), and its x neighbours
+    const uint32_t xA = 2 * pair + colour, xB = 2 * pair + (1 - colour);
+    const uint32_t xpA = (xA + 1 == L) ? 0 : xA + 1, xmA = (xA == 0) ? L - 1 : xA - 1;
+    const uint32_t xpB = (xB + 1 == L) ? 0 : xB + 1, xmB = (xB == 0) ? L - 1 : xB - 1;
+    const uint32_t y1 = min(y0 + a.rows, L);            // y1 - y0 is even
+    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
+    // Software pipeline: the loads of the next row are issued before the
+    // current row is computed.  They never alias its stores: the current
+    // row writes only cells of the updated colour, the next row reads its
+    // own (different) cells and facing arms of the other colour.
+    CellBytes cur = {};
+    if (active) cur = met_load(a, rs, y0, xA, xpA, xmA);
+    met_table(a, tbl, theta);
     uint32_t wsum = 0;
-    if (pair < half && y0 < L) {
-        // column of the updated cell in even rows (A) and odd rows (B), and its x neighbours
-        const uint32_t xA = 2 * pair + colour, xB = 2 * pair + (1 - colour);
-        const uint32_t xpA = (xA + 1 == L) ? 0 : xA + 1, xmA = (xA == 0) ? L - 1 : xA - 1;
-        const uint32_t xpB = (xB + 1 == L) ? 0 : xB + 1, xmB = (xB == 0) ? L - 1 : xB - 1;
-        const uint32_t y1 = min(y0 + a.rows, L);            // y1 - y0 is even
-        const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
-        // Software pipeline: the loads of the next row are issued before the
-        // current row is computed.  They never alias its stores: the current
-        // row writes only cells of the updated colour, the next row reads its
-        // own (different) cells and facing arms of the other colour.
-        CellBytes cur = met_load(a, rs, y0, xA, xpA, xmA);
+    if (active) {
         for (uint32_t y = y0; y < y1; y += 2) {
             const CellBytes odd = met_load(a, rs, y + 1, xB, xpB, xmB);
             met_cell<Q>(a, rs, tbl, t, y, xA, cur, wsum);
@@ -324,12 +331,13 @@ __device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, const u
 template <int Q>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_sweep_kernel(LatticeArgs a, int colour)
 {
-    if (a.st->skip) return;                                // step limit reached
+    const int skip = a.st->skip, theta = a.st->theta;
+    const uint32_t t = a.st->t_cur;
+    if (skip) return;                                      // step limit reached
     // 32 entries: indices d + 16 for d in -15..15, so that even out-of-range
     // bond indices (a caller-supplied configuration) cannot read outside it.
     __shared__ uint2 tbl[32];
-    met_table(a, tbl);
-    const uint32_t wsum = met_byte_block<Q>(a, tbl, a.st->t_cur, colour, blockIdx.x, blockIdx.y);
+    const uint32_t wsum = met_byte_block<Q>(a, tbl, t, theta, colour, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
@@ -351,14 +359,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         else hi = mid;
     }
     const LatticeArgs a = ent[lo].la;
-    if (a.st->skip) return;                                // step limit reached
+    const int skip = a.st->skip, theta = a.st->theta;
+    const uint32_t t = a.st->t_cur;
+    if (skip) return;                                      // step limit reached
     const uint32_t local = blockIdx.x - start[lo];
     const uint32_t gx = ent[lo].groups_x;
     const uint32_t by = local / gx, bx = local - by * gx;
-    met_table(a, tbl);
-    const uint32_t t = a.st->t_cur;
-    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA>(a, tbl, t, bx, by)
-                                 : met_byte_block<Q>(a, tbl, t, KAPPA, bx, by);
+    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA>(a, tbl, t, theta, bx, by)
+                                 : met_byte_block<Q>(a, tbl, t, theta, KAPPA, bx, by);
     met_reduce(wsum, a.slots, local);
 }
 
