@@ -30,7 +30,10 @@ __device__ __forceinline__ void met_arm(uint32_t& s4, uint32_t Z, uint32_t prop,
     // NULL proposal); M in {1, 2, 4} divides 2^32 and has no NULL proposal.
     constexpr bool kHasNull = (M == 3 || M == 5);
     const uint32_t pp = kHasNull ? prop + 1u : prop;
-    const uint32_t kp = (uint32_t)(((uint64_t)pp * M + (1ull << 32)) >> 32);
+    uint32_t kp = (uint32_t)(((uint64_t)pp * M + (1ull << 32)) >> 32);
+    // Empty asm, no instruction: kp stays a 32-bit value, so that 4 kp + s4 is
+    // one v_lshl_add_u32 instead of a 64-bit shift folded into alignbit + and.
+    __asm__("" : "+v"(kp));
     const uint32_t t4 = s4 + (kp << 2);                   // 4 (sigma + 1 + k)
     const uint32_t sn4 = min(t4, t4 - 4u * Q);            // mod q, in units of 4
     const int d = (int)__builtin_amdgcn_ubfe(Z, sn4, 4) - (int)__builtin_amdgcn_ubfe(Z, s4, 4);
