@@ -420,33 +420,67 @@ __global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
     }
 }
 
+// Roots of u and v with both chains followed in lockstep: one memory round
+// trip per step for the pair.  pu, pv: label[u], label[v], already loaded.
+__device__ __forceinline__ void find_roots2(const uint32_t* label, uint32_t& u, uint32_t& v, uint32_t pu,
+                                            uint32_t pv)
+{
+    while (pu != u || pv != v) {
+        u = pu;
+        v = pv;
+        pu = label[u];
+        pv = label[v];
+    }
+}
+
 // Covalent links that leave their tile: +x links of the last column of each
 // tile (and of column L-1, which wraps), +y links of the last row of each
 // tile (and of row L-1).  Thread i < L * ncx handles column-edge cells,
-// the rest row-edge cells.
+// the rest row-edge cells.  Both ends are border bond indices, whose labels
+// the tile kernel wrote; they are read together with the link mask.
 __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint32_t ncx, uint32_t ncy)
 {
     if (a.st->skip) return;
     const uint32_t L = a.L, N = a.N;
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t nx = ncx * L, ny = ncy * L;
+    if (i >= nx + ny) return;
+    uint32_t c, u, v, bit;
     if (i < nx) {
         const uint32_t y = i / ncx, j = i - y * ncx;
         const uint32_t x = min(j * kTW + kTW - 1, L - 1);     // last column of tile j (clamped: x = L-1)
-        const uint32_t c = x + y * L;
-        if (a.mask[c] & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + y * L);
-    } else if (i < nx + ny) {
+        c = x + y * L;
+        u = c;
+        v = N + ((x + 1 == L) ? 0 : x + 1) + y * L;
+        bit = 1;
+    } else {
         const uint32_t r = i - nx;
         const uint32_t x = r / ncy, j = r - x * ncy;
         const uint32_t y = min(j * kTH + kTH - 1, L - 1);
-        const uint32_t c = x + y * L;
-        if (a.mask[c] & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : y + 1) * L);
+        c = x + y * L;
+        u = 2 * N + c;
+        v = 3 * N + x + ((y + 1 == L) ? 0 : y + 1) * L;
+        bit = 2;
+    }
+    const uint32_t m = a.mask[c];
+    const uint32_t pu = a.label[u], pv = a.label[v];
+    if (!(m & bit)) return;
+    find_roots2(a.label, u, v, pu, pv);
+    while (u != v) {                       // union by minimum index, as in unite()
+        if (u > v) {
+            const uint32_t tmp = u;
+            u = v;
+            v = tmp;
+        }
+        const uint32_t old = atomicMin(a.label + v, u);
+        if (old == v) return;
+        v = old;                           // v got a parent meanwhile: unite from there
+        find_roots2(a.label, u, v, a.label[u], a.label[v]);
     }
 }
 
 // Shift sigma of cell c by its clusters' r = pick(w0 of Philox(root, t, 0,
-// SWF), q), NULL -> 0; root = the cluster minimum.  The labels themselves are
-// flattened only when they are read out (sw_flatten_kernel).
+// SWF), q), NULL -> 0; root = the cluster minimum (batched step).
 __device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, uint32_t c)
 {
     const uint32_t N = a.N;
