@@ -407,12 +407,15 @@ struct cvf_batch {
     std::vector<cvf_state*> chains;
     std::vector<BatchEntry> host;     // descriptor source (kept alive for async copies)
     std::vector<uint32_t> start;      // prefix sums of Metropolis workgroups, count + 1
-    std::vector<uint32_t> swstart;    // prefix sums of SW workgroups (256 cells each), count + 1
+    std::vector<uint32_t> tstart;     // prefix sums of SW tiles, count + 1
+    std::vector<uint32_t> estart;     // prefix sums of SW edge-union workgroups, count + 1
     BatchEntry* d_ent;
     uint32_t* d_start;
-    uint32_t* d_swstart;
+    uint32_t* d_tstart;
+    uint32_t* d_estart;
     uint32_t total_blocks;
-    uint32_t sw_blocks;
+    uint32_t sw_tiles;
+    uint32_t sw_edge_blocks;
     bool has_sw;
     int q;
     int32_t rows;                     // 0 = per-chain default
@@ -423,13 +426,16 @@ struct cvf_batch {
 
 namespace {
 
-size_t batch_layout(int32_t count, size_t* off_start, size_t* off_swstart)
+// Descriptor: the entries, then three prefix-sum arrays (Metropolis
+// workgroups, SW tiles, SW edge workgroups).
+size_t batch_layout(int32_t count, size_t* off_start, size_t* off_tstart, size_t* off_estart)
 {
     const size_t ent = align256((size_t)count * sizeof(BatchEntry));
     const size_t st = align256(((size_t)count + 1) * sizeof(uint32_t));
     *off_start = ent;
-    *off_swstart = ent + st;
-    return ent + 2 * st;
+    *off_tstart = ent + st;
+    *off_estart = ent + 2 * st;
+    return ent + 3 * st;
 }
 
 uint32_t met_rows_for(uint32_t L, uint32_t quad, uint32_t target_waves)
@@ -456,8 +462,9 @@ int batch_upload(cvf_batch* b, hipStream_t s)
     const uint32_t count = (uint32_t)b->chains.size();
     b->host.resize(count);
     b->start.assign(count + 1, 0);
-    b->swstart.assign(count + 1, 0);
-    uint32_t total = 0, swtotal = 0;
+    b->tstart.assign(count + 1, 0);
+    b->estart.assign(count + 1, 0);
+    uint32_t total = 0, ttotal = 0, etotal = 0;
     for (uint32_t c = 0; c < count; ++c) {
         const cvf_state* st = b->chains[c];
         BatchEntry& e = b->host[c];
@@ -476,18 +483,26 @@ int batch_upload(cvf_batch* b, hipStream_t s)
         e.blocks = e.groups_x * e.la.row_blocks;
         b->start[c] = total;
         total += e.blocks;
-        b->swstart[c] = swtotal;
-        swtotal += (st->N + 255) / 256;
+        const uint32_t L = (uint32_t)st->p.L;
+        const uint32_t ncx = (L + kTW - 1) / kTW, ncy = (L + kTH - 1) / kTH;
+        b->tstart[c] = ttotal;
+        ttotal += ncx * ncy;
+        b->estart[c] = etotal;
+        etotal += (uint32_t)(((uint64_t)(ncx + ncy) * L + 255) / 256);
     }
     b->start[count] = total;
-    b->swstart[count] = swtotal;
+    b->tstart[count] = ttotal;
+    b->estart[count] = etotal;
     b->total_blocks = total;
-    b->sw_blocks = swtotal;
+    b->sw_tiles = ttotal;
+    b->sw_edge_blocks = etotal;
     hipError_t e = hipMemcpyAsync(b->d_ent, b->host.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_start, b->start.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_swstart, b->swstart.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(b->d_tstart, b->tstart.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_estart, b->estart.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     // the host vectors must stay unchanged until the copies are done
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
@@ -525,8 +540,8 @@ int batch_capture(cvf_batch* b, int32_t block)
 int cvf_batch_desc_bytes(int32_t count, size_t* bytes)
 {
     if (!bytes || count <= 0) return CVF_EINVAL;
-    size_t off, off2;
-    *bytes = batch_layout(count, &off, &off2);
+    size_t off, off2, off3;
+    *bytes = batch_layout(count, &off, &off2, &off3);
     return CVF_OK;
 }
 
@@ -535,8 +550,8 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
 {
     if (!chains || count <= 0 || !d_desc || !out) return CVF_EINVAL;
     if (((uintptr_t)d_desc & 255) != 0) return CVF_EINVAL;
-    size_t off_start, off_swstart;
-    if (desc_bytes < batch_layout(count, &off_start, &off_swstart)) return CVF_ENOMEM;
+    size_t off_start, off_tstart, off_estart;
+    if (desc_bytes < batch_layout(count, &off_start, &off_tstart, &off_estart)) return CVF_ENOMEM;
     for (int32_t c = 0; c < count; ++c)
         if (!chains[c] || chains[c]->p.q != chains[0]->p.q) return CVF_EINVAL;
     cvf_batch* b = new (std::nothrow) cvf_batch();
@@ -544,7 +559,8 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
     b->chains.assign(chains, chains + count);
     b->d_ent = (BatchEntry*)d_desc;
     b->d_start = (uint32_t*)((char*)d_desc + off_start);
-    b->d_swstart = (uint32_t*)((char*)d_desc + off_swstart);
+    b->d_tstart = (uint32_t*)((char*)d_desc + off_tstart);
+    b->d_estart = (uint32_t*)((char*)d_desc + off_estart);
     b->q = chains[0]->p.q;
     b->has_sw = true;
     for (int32_t c = 0; c < count; ++c) b->has_sw = b->has_sw && chains[c]->has_sw && chains[c]->p.Jsigma >= 0.0;
@@ -599,8 +615,9 @@ int cvf_batch_sw_steps(cvf_batch* b, int64_t nsteps, void* stream)
     const uint32_t count = (uint32_t)b->chains.size();
     for (int64_t i = 0; i < nsteps; ++i) {
         hipError_t e = launch_volume_batch(b->d_ent, count, kVolSw, s);
-        for (int stage = 0; stage < 4 && e == hipSuccess; ++stage)
-            e = launch_sw_batch(b->d_ent, b->d_swstart, count, b->sw_blocks, stage, s);
+        if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_tstart, count, b->sw_tiles, 0, s);
+        if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_estart, count, b->sw_edge_blocks, 1, s);
+        if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_tstart, count, b->sw_tiles, 2, s);
         if (e != hipSuccess) return CVF_EHIP;
     }
     return CVF_OK;

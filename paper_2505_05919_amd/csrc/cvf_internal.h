@@ -135,9 +135,11 @@ hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                             int q, int colour, hipStream_t s);
 hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s);
-// Batched Swendsen-Wang stage (0 bonds, 1 union, 2 flip, 3 recount); swstart:
-// count+1 prefix sums of ceil(N/256) workgroups per chain.
-hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint32_t count, uint32_t total_blocks,
+// Batched Swendsen-Wang stage: 0 tiles (bonds + in-tile unions), 1 tile-
+// crossing links, 2 shift + recount; start: count+1 prefix sums of the
+// per-chain workgroups of that stage (tiles for 0 and 2, edge workgroups
+// for 1).
+hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                            int stage, hipStream_t s);
 
 }  // namespace cvf

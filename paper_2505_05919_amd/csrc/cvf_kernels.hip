@@ -415,15 +415,13 @@ hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, 
     return hipGetLastError();
 }
 
-hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* swstart, uint32_t count, uint32_t total_blocks,
+hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                            int stage, hipStream_t s)
 {
-    switch (stage) {
-    case 0: sw_batch_kernel<0><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
-    case 1: sw_batch_kernel<1><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
-    case 2: sw_batch_kernel<2><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
-    default: sw_batch_kernel<3><<<total_blocks, kBlock, 0, s>>>(ent, swstart, count); break;
-    }
+    if (total_blocks == 0) return hipSuccess;
+    if (stage == 0) sw_tile_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
+    else if (stage == 1) sw_edge_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
+    else sw_flip_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
     return hipGetLastError();
 }
 

@@ -164,21 +164,6 @@ __device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwB
     return m;
 }
 
-// Bond activation of cell c, and its labels initialised to the in-cell
-// cooperative components (smallest arm of each component).
-__device__ __forceinline__ void sw_bonds_cell(const LatticeArgs& a, const SwBondCtx& k, const uint8_t* lut,
-                                              uint32_t c, uint32_t x, uint32_t y)
-{
-    const size_t N = a.N;
-    int f0, f2;
-    const uint32_t m = sw_bond_mask(a, k, c, x, y, f0, f2);
-    const uint32_t l4 = lut[m >> 2];
-    a.label[c] = (l4 & 3) * (uint32_t)N + c;
-    a.label[N + c] = ((l4 >> 2) & 3) * (uint32_t)N + c;
-    a.label[2 * N + c] = ((l4 >> 4) & 3) * (uint32_t)N + c;
-    a.label[3 * N + c] = ((l4 >> 6) & 3) * (uint32_t)N + c;
-}
-
 // Root of x: follow parents until a self-loop.  label[x] <= x everywhere, so
 // the chain strictly decreases and ends.
 __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
@@ -189,37 +174,6 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
         p = label[x];
     }
     return x;
-}
-
-// Lock-free union by minimum index (atomicMin on the larger root).  A failed
-// attempt means the larger root got a parent meanwhile; that parent is then
-// united with the smaller root, so no connection is lost.  The largest of
-// the two roots strictly decreases each round.
-__device__ void unite(uint32_t* label, uint32_t a, uint32_t b)
-{
-    a = find_root(label, a);
-    b = find_root(label, b);
-    while (a != b) {
-        if (a > b) {
-            const uint32_t tmp = a;
-            a = b;
-            b = tmp;
-        }
-        const uint32_t old = atomicMin(label + b, a);
-        if (old == b) return;
-        b = find_root(label, old);
-        a = find_root(label, a);
-    }
-}
-
-__device__ __forceinline__ void sw_union_cell(const LatticeArgs& a, uint32_t c, uint32_t x, uint32_t y)
-{
-    const uint32_t L = a.L, N = a.N;
-    const uint32_t m = a.mask[c];
-    if (!(m & 3)) return;
-    const uint32_t row = y * L;
-    if (m & 1) unite(a.label, c, N + ((x + 1 == L) ? 0 : x + 1) + row);
-    if (m & 2) unite(a.label, 2 * N + c, 3 * N + x + ((y + 1 == L) ? 0 : row + L));
 }
 
 // ---------------------------------------------------------------------------
@@ -250,16 +204,20 @@ struct TileGeom {
     uint32_t x0, y0, w, h, id;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(uint32_t L)
+// Tile (bx, by) of a lattice with ncx tiles per row.
+__device__ __forceinline__ TileGeom tile_geom(uint32_t L, uint32_t bx, uint32_t by, uint32_t ncx)
 {
     TileGeom g;
-    g.x0 = blockIdx.x * kTW;
-    g.y0 = blockIdx.y * kTH;
+    g.x0 = bx * kTW;
+    g.y0 = by * kTH;
     g.w = min(kTW, L - g.x0);
     g.h = min(kTH, L - g.y0);
-    g.id = blockIdx.x + blockIdx.y * gridDim.x;
+    g.id = bx + by * ncx;
     return g;
 }
+
+// The tile of this workgroup in a single-chain launch (grid = tiles).
+__device__ __forceinline__ TileGeom grid_tile(uint32_t L) { return tile_geom(L, blockIdx.x, blockIdx.y, gridDim.x); }
 
 __device__ __forceinline__ bool tile_in(const TileGeom& g, uint32_t v)
 {
@@ -367,15 +325,12 @@ __device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom&
     }
 }
 
-__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+// lut: 64 bytes, lab: 4 kTC words of LDS.
+__device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeom& g, uint8_t* lut, uint32_t* lab)
 {
-    if (a.st->skip) return;
-    __shared__ uint8_t lut[64];
-    __shared__ uint32_t lab[4 * kTC];
     build_incell_lut(lut);
     const SwBondCtx k = sw_ctx(a);
     const uint32_t L = a.L, N = a.N;
-    const TileGeom g = tile_geom(L);
     uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
     uint32_t mk[kTC / 256];
 #pragma unroll
@@ -420,6 +375,14 @@ __global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+{
+    if (a.st->skip) return;
+    __shared__ uint8_t lut[64];
+    __shared__ uint32_t lab[4 * kTC];
+    sw_tile_body(a, grid_tile(a.L), lut, lab);
+}
+
 // Roots of u and v with both chains followed in lockstep: one memory round
 // trip per step for the pair.  pu, pv: label[u], label[v], already loaded.
 __device__ __forceinline__ void find_roots2(const uint32_t* label, uint32_t& u, uint32_t& v, uint32_t pu,
@@ -438,11 +401,9 @@ __device__ __forceinline__ void find_roots2(const uint32_t* label, uint32_t& u, 
 // tile (and of row L-1).  Thread i < L * ncx handles column-edge cells,
 // the rest row-edge cells.  Both ends are border bond indices, whose labels
 // the tile kernel wrote; they are read together with the link mask.
-__global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint32_t ncx, uint32_t ncy)
+__device__ __forceinline__ void sw_edge_body(const LatticeArgs& a, uint32_t i, uint32_t ncx, uint32_t ncy)
 {
-    if (a.st->skip) return;
     const uint32_t L = a.L, N = a.N;
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t nx = ncx * L, ny = ncy * L;
     if (i >= nx + ny) return;
     uint32_t c, u, v, bit;
@@ -466,7 +427,11 @@ __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint
     const uint32_t pu = a.label[u], pv = a.label[v];
     if (!(m & bit)) return;
     find_roots2(a.label, u, v, pu, pv);
-    while (u != v) {                       // union by minimum index, as in unite()
+    // Lock-free union by minimum index: atomicMin points the larger root at the
+    // smaller.  A failed attempt means the larger root got a parent meanwhile;
+    // the union continues from that parent, so no connection is lost, and the
+    // larger of the two roots strictly decreases each round.
+    while (u != v) {
         if (u > v) {
             const uint32_t tmp = u;
             u = v;
@@ -479,35 +444,31 @@ __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint
     }
 }
 
-// Shift sigma of cell c by its clusters' r = pick(w0 of Philox(root, t, 0,
-// SWF), q), NULL -> 0; root = the cluster minimum (batched step).
-__device__ __forceinline__ void sw_flip_cell(const LatticeArgs& a, uint32_t t, uint32_t c)
-{
-    const uint32_t N = a.N;
-    const int q = (int)a.q;
-#pragma unroll
-    for (int arm = 0; arm < 4; ++arm) {
-        const uint32_t idx = arm * N + c;
-        const uint32_t r = find_root(a.label, idx);
-        const uint32_t w = philox(r, t, 0u, kStreamSwf, a.key0, a.key1).x;
-        const int k = (w <= a.flip_lim) ? (int)((double)w * a.flip_invd) : 0;
-        int sv = a.sigma[idx] + k;
-        sv = sv >= q ? sv - q : sv;
-        a.sigma[idx] = (uint8_t)sv;
-    }
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
+__global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint32_t ncx, uint32_t ncy)
 {
     if (a.st->skip) return;
-    __shared__ uint16_t roots[4 * kTC];      // component roots (| kBorder), compacted; then the new sigma
-    __shared__ uint8_t sh[4 * kTC];          // shift of each component root
-    __shared__ uint8_t across[kEdgeBytes];   // new sigma facing the right / bottom edge
-    __shared__ uint32_t nroot;
+    sw_edge_body(a, blockIdx.x * 256 + threadIdx.x, ncx, ncy);
+}
+
+// LDS of the flip: the compacted component roots (| kBorder), whose space
+// then holds the new sigma of the tile; the shift of each root; the new
+// sigma facing the right / bottom edge; the root count.
+struct FlipLds {
+    uint16_t roots[4 * kTC];
+    uint8_t sh[4 * kTC];
+    uint8_t across[kEdgeBytes];
+    uint32_t nroot;
+};
+
+__device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeom& g, FlipLds& lds)
+{
+    uint16_t* roots = lds.roots;
+    uint8_t* sh = lds.sh;
+    uint8_t* across = lds.across;
+    uint32_t& nroot = lds.nroot;
     uint8_t* nsg = reinterpret_cast<uint8_t*>(roots);
     if (threadIdx.x == 0) nroot = 0;
     const uint32_t L = a.L, N = a.N, q = a.q;
-    const TileGeom g = tile_geom(L);
     const uint32_t t = a.st->t_cur;
     if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
     // entry i: plane i / 4, tile row wave + 4 (i % 4), column lane
@@ -529,25 +490,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             if (col_in) lr[i] = l;
         }
     }
-    // component roots, compacted: one LDS atomic per wavefront
-    uint64_t bal[4 * kTC / 256];
+    // component roots, compacted: one LDS atomic per wavefront (the ballots
+    // are taken twice rather than kept: 16 of them would not fit in SGPRs)
+    auto is_root = [&](uint32_t i) {
+        return col_in && ent_row(wave, i) < g.h && (lr[i] & kIdx) == ent_local(wave, lane, i);
+    };
     uint32_t cnt = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
-        const uint32_t v = ent_local(wave, lane, i);
-        bal[i] = __ballot(col_in && ent_row(wave, i) < g.h && (lr[i] & kIdx) == v);
-        cnt += (uint32_t)__popcll(bal[i]);
-    }
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) cnt += (uint32_t)__popcll(__ballot(is_root(i)));
     __syncthreads();                          // nroot = 0
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&nroot, cnt);
     base = (uint32_t)__shfl((int)base, 0);
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+        const bool root = is_root(i);
+        const uint64_t bal = __ballot(root);
         const uint32_t pos =
-            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[i] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[i], 0u));
-        if ((bal[i] >> lane) & 1) roots[pos] = (uint16_t)lr[i];
-        base += (uint32_t)__popcll(bal[i]);
+            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (root) roots[pos] = (uint16_t)lr[i];
+        base += (uint32_t)__popcll(bal);
     }
     __syncthreads();
     // Jobs: one shift per component root, then the facing arms across the
@@ -643,6 +605,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     block_add<2>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
 }
 
+__global__ __launch_bounds__(256) void sw_flip_tile_kernel(LatticeArgs a)
+{
+    if (a.st->skip) return;
+    __shared__ FlipLds lds;
+    sw_flip_body(a, grid_tile(a.L), lds);
+}
+
 // label[idx] = the minimum of idx's cluster, for every bond index; written
 // to out (4N uint32).  Works from the mask and the global labels left by
 // either the tiled or the batched step.
@@ -652,7 +621,7 @@ __global__ __launch_bounds__(256) void sw_labels_kernel(LatticeArgs a, uint32_t*
     __shared__ uint32_t lab[4 * kTC];
     build_incell_lut(lut);
     const uint32_t L = a.L, N = a.N;
-    const TileGeom g = tile_geom(L);
+    const TileGeom g = grid_tile(L);
     uint32_t mk[kTC / 256];
     tile_masks(a, g, mk);
     __syncthreads();
@@ -668,8 +637,10 @@ __global__ __launch_bounds__(256) void sw_labels_kernel(LatticeArgs a, uint32_t*
 }
 
 // ---------------------------------------------------------------------------
-// Batched Swendsen-Wang: workgroup b belongs to the chain c with
-// swstart[c] <= b < swstart[c+1] and covers its cells 256 (b - swstart[c]) ..
+// Batched Swendsen-Wang: the tiled step of every chain of a batch, one launch
+// per stage.  Workgroup b belongs to the chain c with start[c] <= b <
+// start[c+1] (prefix sums of per-chain tiles, or of edge workgroups) and does
+// exactly what the workgroup of that chain's own launch does.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t count, uint32_t b)
 {
@@ -682,35 +653,40 @@ __device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t 
     return lo;
 }
 
-// stage 0 bonds, 1 union, 2 flip, 3 recount
-template <int STAGE>
-__global__ __launch_bounds__(kBlock) void sw_batch_kernel(const BatchEntry* __restrict__ ent,
-                                                          const uint32_t* __restrict__ swstart, uint32_t count)
+__device__ __forceinline__ TileGeom batch_tile(const LatticeArgs& a, uint32_t local)
+{
+    const uint32_t ncx = (a.L + kTW - 1) / kTW;
+    const uint32_t by = local / ncx;
+    return tile_geom(a.L, local - by * ncx, by, ncx);
+}
+
+__global__ __launch_bounds__(256) void sw_tile_batch_kernel(const BatchEntry* __restrict__ ent,
+                                                            const uint32_t* __restrict__ tstart, uint32_t count)
 {
     __shared__ uint8_t lut[64];
-    const uint32_t ch = batch_chain(swstart, count, blockIdx.x);
-    const LatticeArgs a = ent[ch].la;
+    __shared__ uint32_t lab[4 * kTC];
+    const uint32_t c = batch_chain(tstart, count, blockIdx.x);
+    const LatticeArgs a = ent[c].la;
     if (a.st->skip) return;
-    const uint32_t local = blockIdx.x - swstart[ch];
-    const uint32_t c = local * kBlock + threadIdx.x;
-    const bool in = c < a.N;
-    uint32_t x = 0, y = 0;
-    if (in) y = divmod(c, a.L, 1.0 / (double)a.L, x);
-    if (STAGE == 0) {
-        build_incell_lut(lut);
-        __syncthreads();
-        const SwBondCtx k = sw_ctx(a);
-        if (in) sw_bonds_cell(a, k, lut, c, x, y);
-    } else if (STAGE == 1) {
-        if (in) sw_union_cell(a, c, x, y);
-    } else if (STAGE == 2) {
-        const uint32_t t = a.st->t_cur;
-        if (local == 0 && threadIdx.x == 0) a.st->sw_done = 1;
-        if (in) sw_flip_cell(a, t, c);
-    } else {
-        int hb = 0, co = 0;
-        if (in) recount_cell(a, c, x, y, hb, co, nullptr);
-        const int v[2] = {hb, co};
-        block_add<2>(v, a.slots + (local & (kSlots - 1)), kSlots);
-    }
+    sw_tile_body(a, batch_tile(a, blockIdx.x - tstart[c]), lut, lab);
+}
+
+__global__ __launch_bounds__(256) void sw_edge_batch_kernel(const BatchEntry* __restrict__ ent,
+                                                            const uint32_t* __restrict__ estart, uint32_t count)
+{
+    const uint32_t c = batch_chain(estart, count, blockIdx.x);
+    const LatticeArgs a = ent[c].la;
+    if (a.st->skip) return;
+    const uint32_t ncx = (a.L + kTW - 1) / kTW, ncy = (a.L + kTH - 1) / kTH;
+    sw_edge_body(a, (blockIdx.x - estart[c]) * 256 + threadIdx.x, ncx, ncy);
+}
+
+__global__ __launch_bounds__(256) void sw_flip_batch_kernel(
+    const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ tstart, uint32_t count)
+{
+    __shared__ FlipLds lds;
+    const uint32_t c = batch_chain(tstart, count, blockIdx.x);
+    const LatticeArgs a = ent[c].la;
+    if (a.st->skip) return;
+    sw_flip_body(a, batch_tile(a, blockIdx.x - tstart[c]), lds);
 }
