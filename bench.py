@@ -208,6 +208,7 @@ def bench_served(torch, n_jobs):
             "makespan_s": round(s["makespan_s"], 3), "met_updates_per_ns": round(s["met_updates_per_ns"], 1),
             "offered_met_updates_per_ns": round(offered, 1),
             "peak_resident_jobs": srv.peak_resident_jobs, "peak_resident_MB": round(srv.peak_resident_bytes / 2**20, 1),
+            "quanta": srv.quanta, "loop_phase_s": {k: round(v, 3) for k, v in srv.phase_s.items()},
             "one_at_a_time": {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
                               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
                               "makespan_s": round(done - min(j.arrival for j in jobs), 3),

@@ -69,6 +69,10 @@ class Server:
     peak_resident_bytes: int = 0
     peak_resident_jobs: int = 0
     quanta: int = 0
+    # wall seconds per part of the loop: admission (chain creation), enqueueing
+    # the quantum's launches (and batch rebuilds), waiting for the GPU, retiring
+    # finished jobs (observables, digests)
+    phase_s: dict = field(default_factory=lambda: {"admit": 0.0, "launch": 0.0, "wait": 0.0, "retire": 0.0})
 
     def run(self, jobs: list[Job], realtime: bool = True) -> list[Record]:
         """Serve `jobs` (sorted by arrival).  realtime: arrivals are released
@@ -92,6 +96,7 @@ class Server:
 
         while pending or queue or running:
             tnow = now()
+            tp = time.perf_counter()
             while pending and (not realtime or pending[0].arrival <= tnow):
                 queue.append(pending.pop(0))
             # admission: FIFO, by footprint and slots
@@ -114,6 +119,8 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now(), 0.002)))
                 continue
+            tq = time.perf_counter()
+            self.phase_s["admit"] += tq - tp
             met = [r for r in running if r.job.algo == "met"]
             sws = [r for r in running if r.job.algo == "sw"]
             # one quantum: every resident job advances by min(quantum, remaining) steps
@@ -139,9 +146,13 @@ class Server:
                 swb.sw(n)
                 for r in sws:
                     r.done = min(r.done + n, r.job.nsteps)
+            tl = time.perf_counter()
+            self.phase_s["launch"] += tl - tq
             torch.cuda.synchronize()
             self.quanta += 1
             tdone = now()
+            tw = time.perf_counter()
+            self.phase_s["wait"] += tw - tl
             still = []
             for r in running:
                 if r.done >= r.job.nsteps:
@@ -163,6 +174,7 @@ class Server:
                 swb.close()
                 swb = None
             running = still
+            self.phase_s["retire"] += time.perf_counter() - tw
         if batch is not None:
             batch.close()
         if swb is not None:
