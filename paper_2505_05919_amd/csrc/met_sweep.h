@@ -245,6 +245,26 @@ __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32
     block_add<3>(v, slots + (slot & (kSlots - 1)), kSlots);
 }
 
+// The waves of a SIMD are issued oldest first, so with equal work the oldest
+// finish early and the SIMD ends the pass with few waves and poor latency
+// hiding.  Lowering a wave's priority (s_setprio 3 -> 0) as it advances
+// through its rows lets the laggards catch up: all waves stay resident until
+// the last quarter of the pass.  it: the wave's row-pair index, n: its count.
+struct ProgressPrio {
+    uint32_t t1, t2, t3;                      // first row-pair index of levels 2, 1, 0
+    __device__ __forceinline__ explicit ProgressPrio(uint32_t n)
+        : t1((n + 3) / 4), t2((2 * n + 3) / 4), t3((3 * n + 3) / 4)
+    {
+        __builtin_amdgcn_s_setprio(3);
+    }
+    __device__ __forceinline__ void step(uint32_t it) const
+    {
+        if (it == t1) __builtin_amdgcn_s_setprio(2);
+        if (it == t2) __builtin_amdgcn_s_setprio(1);
+        if (it == t3) __builtin_amdgcn_s_setprio(0);
+    }
+};
+
 // One workgroup's share of a colour pass with quad lanes: column group bx
 // (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  The first
 // row's loads are issued before the LDS table is built, so both latencies
@@ -270,7 +290,9 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
     if (active) {
+        const ProgressPrio prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
+            prio.step((y - y0) >> 1);
             const QuadBytes odd = met_load4<PO>(a, rs, y + 1, x4, xl, xr);
             met_quad<Q, PE>(a, rs, tbl, t, y, x4, cur, wsum);
             const uint32_t yn = (y + 2 < y1) ? y + 2 : y;
@@ -320,7 +342,9 @@ __device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, uint2* 
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
     if (active) {
+        const ProgressPrio prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
+            prio.step((y - y0) >> 1);
             const CellBytes odd = met_load(a, rs, y + 1, xB, xpB, xmB);
             met_cell<Q>(a, rs, tbl, t, y, xA, cur, wsum);
             const uint32_t yn = (y + 2 < y1) ? y + 2 : y;     // last pair: a harmless re-read
