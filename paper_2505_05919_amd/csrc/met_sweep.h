@@ -303,10 +303,12 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     return wsum;
 }
 
-// 8 wavefronts per SIMD (<= 64 VGPRs): the latency of the row loads and of the
-// LDS table lookups is hidden by the other waves.
+// No occupancy cap: the quad loop needs ~80 VGPRs (6 wavefronts per SIMD).
+// Capping it at 64 VGPRs for 8 wavefronts spills to scratch and measured
+// slower; with the progress priority the 2048-workgroup grid runs as one full
+// round plus a short second one.
 template <int Q, int KAPPA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_sweep4_kernel(LatticeArgs a)
+__global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
 {
     const int skip = a.st->skip, theta = a.st->theta;
     const uint32_t t = a.st->t_cur;
@@ -374,6 +376,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // is the workgroup (bx, by) of that chain's own launch shape, so every chain
 // computes exactly what its own launch computes.
 // ---------------------------------------------------------------------------
+// Batches are mostly small lattices (many workgroups of few rows): here the
+// 8-wavefront occupancy measured faster than the uncapped register budget.
 template <int Q, int KAPPA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_batch_kernel(
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ start, uint32_t count)
