@@ -250,15 +250,19 @@ __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32
 // hiding.  Lowering a wave's priority (s_setprio 3 -> 0) as it advances
 // through its rows lets the laggards catch up: all waves stay resident until
 // the last quarter of the pass.  it: the wave's row-pair index, n: its count.
+// (Batched passes, whose workgroups belong to lattices of different sizes,
+// measured faster without it: ON = false.)
+template <bool ON>
 struct ProgressPrio {
     uint32_t t1, t2, t3;                      // first row-pair index of levels 2, 1, 0
     __device__ __forceinline__ explicit ProgressPrio(uint32_t n)
         : t1((n + 3) / 4), t2((2 * n + 3) / 4), t3((3 * n + 3) / 4)
     {
-        __builtin_amdgcn_s_setprio(3);
+        if (ON) __builtin_amdgcn_s_setprio(3);
     }
     __device__ __forceinline__ void step(uint32_t it) const
     {
+        if (!ON) return;
         if (it == t1) __builtin_amdgcn_s_setprio(2);
         if (it == t2) __builtin_amdgcn_s_setprio(1);
         if (it == t3) __builtin_amdgcn_s_setprio(0);
@@ -269,7 +273,7 @@ struct ProgressPrio {
 // (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  The first
 // row's loads are issued before the LDS table is built, so both latencies
 // overlap.  Returns the lane's packed counter sum.
-template <int Q, int KAPPA>
+template <int Q, int KAPPA, bool PRIO>
 __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
                                                    uint32_t bx, uint32_t by)
 {
@@ -290,7 +294,7 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
     if (active) {
-        const ProgressPrio prio((y1 - y0) >> 1);
+        const ProgressPrio<PRIO> prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
             prio.step((y - y0) >> 1);
             const QuadBytes odd = met_load4<PO>(a, rs, y + 1, x4, xl, xr);
@@ -314,12 +318,12 @@ __global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
     const uint32_t t = a.st->t_cur;
     if (skip) return;                                      // step limit reached
     __shared__ uint2 tbl[32];
-    const uint32_t wsum = met_quad_block<Q, KAPPA>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
+    const uint32_t wsum = met_quad_block<Q, KAPPA, true>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // Byte-lane variant (any even L): lane i owns the column pair (2i, 2i+1).
-template <int Q>
+template <int Q, bool PRIO>
 __device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
                                                    int colour, uint32_t bx, uint32_t by)
 {
@@ -344,7 +348,7 @@ __device__ __forceinline__ uint32_t met_byte_block(const LatticeArgs& a, uint2* 
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
     if (active) {
-        const ProgressPrio prio((y1 - y0) >> 1);
+        const ProgressPrio<PRIO> prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
             prio.step((y - y0) >> 1);
             const CellBytes odd = met_load(a, rs, y + 1, xB, xpB, xmB);
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     // 32 entries: indices d + 16 for d in -15..15, so that even out-of-range
     // bond indices (a caller-supplied configuration) cannot read outside it.
     __shared__ uint2 tbl[32];
-    const uint32_t wsum = met_byte_block<Q>(a, tbl, t, theta, colour, blockIdx.x, blockIdx.y);
+    const uint32_t wsum = met_byte_block<Q, true>(a, tbl, t, theta, colour, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
@@ -396,8 +400,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const uint32_t local = blockIdx.x - start[lo];
     const uint32_t gx = ent[lo].groups_x;
     const uint32_t by = local / gx, bx = local - by * gx;
-    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA>(a, tbl, t, theta, bx, by)
-                                 : met_byte_block<Q>(a, tbl, t, theta, KAPPA, bx, by);
+    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA, false>(a, tbl, t, theta, bx, by)
+                                 : met_byte_block<Q, false>(a, tbl, t, theta, KAPPA, bx, by);
     met_reduce(wsum, a.slots, local);
 }
 
