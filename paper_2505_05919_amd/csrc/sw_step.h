@@ -328,6 +328,10 @@ __device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom&
 // lut: 64 bytes, lab: 4 kTC words of LDS.
 __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeom& g, uint8_t* lut, uint32_t* lab)
 {
+    // Waves of a SIMD issue oldest first; a workgroup that has finished its
+    // bonds yields to those still computing theirs, so all tiles reach the
+    // latency-bound union phases together (priority 3, 2, 0 by phase).
+    __builtin_amdgcn_s_setprio(3);
     build_incell_lut(lut);
     const SwBondCtx k = sw_ctx(a);
     const uint32_t L = a.L, N = a.N;
@@ -346,8 +350,10 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
         }
         mk[i] = m;
     }
+    __builtin_amdgcn_s_setprio(2);
     __syncthreads();
     tile_components(lab, lut, mk, g);
+    __builtin_amdgcn_s_setprio(0);
     // every bond index: its tile-local root (| flag); flagged roots: a
     // global self-label; border bond indices: a global label of their root
     const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
