@@ -80,6 +80,15 @@ def lib():
         L.ocvf_params_from_si.argtypes = [ctypes.c_double, ctypes.c_double, P]
         L.ocvf_tables.argtypes = [P, u32p, u64p]
         L.ocvf_components.argtypes = [ctypes.c_int32, u8p, u32p]
+        L.ocvf_init_cell.argtypes = [P, ctypes.c_int64, u8p]
+        L.ocvf_met_cell.argtypes = [P, u32p, ctypes.c_int64, ctypes.c_uint32, u8p, u8p,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64)]
+        L.ocvf_sw_cell_mask.argtypes = [P, u64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, u8p,
+                                        ctypes.c_uint8, ctypes.c_uint8]
+        L.ocvf_sw_cell_mask.restype = ctypes.c_uint8
+        L.ocvf_sw_shift.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32]
+        L.ocvf_sw_shift.restype = ctypes.c_int32
         L.ocvf_create.argtypes = [P]
         L.ocvf_create.restype = ctypes.c_void_p
         L.ocvf_destroy.argtypes = [ctypes.c_void_p]
@@ -142,6 +151,38 @@ def tables(p: Params):
     sw = np.zeros(3, dtype=np.uint64)
     lib().ocvf_tables(ctypes.byref(p), _ptr(met, ctypes.c_uint32), _ptr(sw, ctypes.c_uint64))
     return met, sw
+
+
+def init_cell(p: Params, c: int) -> np.ndarray:
+    """Initial bond indices of cell c (uint8[4])."""
+    out = np.zeros(4, dtype=np.uint8)
+    lib().ocvf_init_cell(ctypes.byref(p), c, _ptr(out, ctypes.c_uint8))
+    return out
+
+
+def met_cell(p: Params, tab: np.ndarray, c: int, t: int, s4, f4):
+    """Metropolis update of the four arms of cell c at step t (tab: uint32[3][7]
+    of the current theta).  Returns (new s4, d_hb, d_coop, accepted)."""
+    s = np.ascontiguousarray(np.asarray(s4, dtype=np.uint8)).copy()
+    f = np.ascontiguousarray(np.asarray(f4, dtype=np.uint8))
+    tb = np.ascontiguousarray(np.asarray(tab, dtype=np.uint32))
+    dh, dc, na = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().ocvf_met_cell(ctypes.byref(p), _ptr(tb, ctypes.c_uint32), c, t, _ptr(s, ctypes.c_uint8),
+                        _ptr(f, ctypes.c_uint8), ctypes.byref(dh), ctypes.byref(dc), ctypes.byref(na))
+    return s, dh.value, dc.value, na.value
+
+
+def sw_cell_mask(p: Params, sw: np.ndarray, theta: int, c: int, t: int, s4, f0: int, f2: int) -> int:
+    """Bond mask of cell c at step t."""
+    s = np.ascontiguousarray(np.asarray(s4, dtype=np.uint8))
+    w = np.ascontiguousarray(np.asarray(sw, dtype=np.uint64))
+    return int(lib().ocvf_sw_cell_mask(ctypes.byref(p), _ptr(w, ctypes.c_uint64), theta, c, t,
+                                       _ptr(s, ctypes.c_uint8), f0, f2))
+
+
+def sw_shift(p: Params, root: int, t: int) -> int:
+    """Shift of the cluster with minimum index root at step t."""
+    return int(lib().ocvf_sw_shift(ctypes.byref(p), root, t))
 
 
 def components(L: int, mask: np.ndarray) -> np.ndarray:

@@ -209,6 +209,15 @@ static void count(const ocvf_state *s, int64_t *hb, int64_t *coop, int64_t *cnt)
     *coop = k;
 }
 
+/* Initial configuration of cell c: sigma[a] = floor(w_a q / 2^32) with
+ * (w0..w3) = Philox(c, 0, 0, INIT). */
+void ocvf_init_cell(const ocvf_params *p, int64_t c, uint8_t s4[4])
+{
+    uint32_t w[4];
+    philox((uint32_t)c, 0, 0, OCVF_INIT, p->seed, w);
+    for (int a = 0; a < 4; ++a) s4[a] = (uint8_t)(((uint64_t)w[a] * (uint64_t)p->q) >> 32);
+}
+
 ocvf_state *ocvf_create(const ocvf_params *p)
 {
     ocvf_state *s = (ocvf_state *)calloc(1, sizeof(*s));
@@ -218,12 +227,10 @@ ocvf_state *ocvf_create(const ocvf_params *p)
     s->mask = (uint8_t *)calloc((size_t)s->N, 1);
     s->label = (uint32_t *)calloc((size_t)(4 * s->N), sizeof(uint32_t));
     ocvf_tables(p, s->met, s->sw);
-    /* initial configuration: sigma[a][c] = floor(w_a q / 2^32) */
     for (int64_t c = 0; c < s->N; ++c) {
-        uint32_t w[4];
-        philox((uint32_t)c, 0, 0, OCVF_INIT, p->seed, w);
-        for (int a = 0; a < 4; ++a)
-            s->sigma[a * s->N + c] = (uint8_t)(((uint64_t)w[a] * (uint64_t)p->q) >> 32);
+        uint8_t s4[4];
+        ocvf_init_cell(p, c, s4);
+        for (int a = 0; a < 4; ++a) s->sigma[a * s->N + c] = s4[a];
     }
     s->v = p->v_init;
     s->theta = s->v < 2.0;                        /* gas-like iff v >= 2 */
@@ -281,43 +288,61 @@ static void volume_move(ocvf_state *s)
 /* proposal uniform over the q-1 other states, dh against the facing arm,    */
 /* dc against the three other arms, accept through the table.               */
 /* ------------------------------------------------------------------------ */
+/* The four arms of cell c at step t, in order 0..3: s4 the cell's bond
+ * indices (updated in place), f4[a] the facing bond index of arm a (arm a^1
+ * of the neighbour in direction a -- of the other colour, so fixed while the
+ * cell moves), tab the acceptance table of the current theta.  Adds the
+ * accepted changes of N_HB_raw and N_sigma and the acceptance count. */
+void ocvf_met_cell(const ocvf_params *p, const uint32_t tab[3][7], int64_t c, uint32_t t, uint8_t s4[4],
+                   const uint8_t f4[4], int64_t *d_hb, int64_t *d_coop, int64_t *n_acc)
+{
+    const int32_t q = p->q;
+    for (int a = 0; a < 4; ++a) {
+        uint32_t w[4];
+        philox((uint32_t)c, t, (uint32_t)(a >> 1), OCVF_MET, p->seed, w);
+        uint32_t prop = (a & 1) ? w[2] : w[0];
+        uint32_t accw = (a & 1) ? w[3] : w[1];
+        int32_t k = ocvf_pick(prop, (uint32_t)(q - 1));
+        if (k < 0) continue;                       /* null move */
+        int32_t old = s4[a];
+        int32_t neu = (old + 1 + k) % q;
+        int32_t facing = f4[a];
+        int32_t dh = (neu == facing) - (old == facing);
+        int32_t dc = 0;
+        for (int b = 0; b < 4; ++b) {
+            if (b == a) continue;
+            int32_t sb = s4[b];
+            dc += (neu == sb) - (old == sb);
+        }
+        uint32_t thr = tab[dh + 1][dc + 3];
+        if (thr == 0xFFFFFFFFu || accw < thr) {
+            s4[a] = (uint8_t)neu;
+            *d_hb += dh;
+            *d_coop += dc;
+            ++*n_acc;
+        }
+    }
+}
+
 static void metropolis_sweep(ocvf_state *s)
 {
-    const int32_t L = s->p.L, q = s->p.q;
+    const int32_t L = s->p.L;
     const int64_t N = s->N;
     uint8_t *sg = s->sigma;
-    const uint32_t (*tab)[7] = s->met[s->theta];
     for (int colour = 0; colour < 2; ++colour) {
         for (int32_t y = 0; y < L; ++y) {
             for (int32_t x = 0; x < L; ++x) {
                 if (((x + y) & 1) != colour) continue;
                 int64_t c = x + (int64_t)L * y;
+                uint8_t s4[4], f4[4];
                 for (int a = 0; a < 4; ++a) {
-                    uint32_t w[4];
-                    philox((uint32_t)c, (uint32_t)s->t, (uint32_t)(a >> 1), OCVF_MET, s->p.seed, w);
-                    uint32_t prop = (a & 1) ? w[2] : w[0];
-                    uint32_t accw = (a & 1) ? w[3] : w[1];
-                    s->met_att++;
-                    int32_t k = ocvf_pick(prop, (uint32_t)(q - 1));
-                    if (k < 0) continue;                       /* null move */
-                    int32_t old = sg[a * N + c];
-                    int32_t neu = (old + 1 + k) % q;
-                    int32_t facing = sg[(a ^ 1) * N + nb(L, c, a)];
-                    int32_t dh = (neu == facing) - (old == facing);
-                    int32_t dc = 0;
-                    for (int b = 0; b < 4; ++b) {
-                        if (b == a) continue;
-                        int32_t sb = sg[b * N + c];
-                        dc += (neu == sb) - (old == sb);
-                    }
-                    uint32_t thr = tab[dh + 1][dc + 3];
-                    if (thr == 0xFFFFFFFFu || accw < thr) {
-                        sg[a * N + c] = (uint8_t)neu;
-                        s->n_hb_raw += dh;
-                        s->n_coop += dc;
-                        s->met_acc++;
-                    }
+                    s4[a] = sg[a * N + c];
+                    f4[a] = sg[(a ^ 1) * N + nb(L, c, a)];
                 }
+                ocvf_met_cell(&s->p, s->met[s->theta], c, (uint32_t)s->t, s4, f4, &s->n_hb_raw, &s->n_coop,
+                              &s->met_acc);
+                s->met_att += 4;
+                for (int a = 0; a < 4; ++a) sg[a * N + c] = s4[a];
             }
         }
     }
@@ -392,44 +417,62 @@ void ocvf_components(int32_t L, const uint8_t *mask, uint32_t *label)
 /* every cluster draws rnd_int in {0..q-1} (keyed by its label) and all its  */
 /* sigma become (sigma + rnd_int) % q.                                       */
 /* ------------------------------------------------------------------------ */
+/* Bond activation of cell c at step t (Sec. II.D, step 1): s4 its bond
+ * indices, f0 / f2 the facing bond indices of its arms 0 and 2 (arm 1 of the
+ * +x neighbour, arm 3 of the +y neighbour).  Link l uses word l of
+ * Philox(c, t, 0, SWB) for l < 4 and word l-4 of Philox(c, t, 1, SWB).
+ * Returns the 8-bit link mask. */
+uint8_t ocvf_sw_cell_mask(const ocvf_params *p, const uint64_t sw[3], int32_t theta, int64_t c, uint32_t t,
+                          const uint8_t s4[4], uint8_t f0, uint8_t f2)
+{
+    double Jeff = p->J - p->P * p->vHB;
+    uint64_t thr_sigma = sw[0];
+    uint64_t thr_eff = sw[1 + theta];
+    uint32_t w0[4], w1[4], w[8];
+    philox((uint32_t)c, t, 0, OCVF_SWB, p->seed, w0);
+    philox((uint32_t)c, t, 1, OCVF_SWB, p->seed, w1);
+    for (int i = 0; i < 4; ++i) { w[i] = w0[i]; w[4 + i] = w1[i]; }
+    uint8_t m = 0;
+    for (int l = 0; l < 2; ++l) {
+        int eq = s4[2 * l] == (l == 0 ? f0 : f2);            /* arm 0 or 2 against its partner */
+        int bond = 0;
+        if (theta == 1) {
+            if (Jeff > 0.0) bond = eq && (uint64_t)w[l] < thr_eff;
+            else if (Jeff < 0.0) bond = !eq && (uint64_t)w[l] < thr_eff;
+        }
+        if (bond) m |= (uint8_t)(1u << l);
+    }
+    for (int l = 0; l < 6; ++l) {
+        int eq = s4[pair_a[l]] == s4[pair_b[l]];
+        if (eq && (uint64_t)w[2 + l] < thr_sigma) m |= (uint8_t)(1u << (2 + l));
+    }
+    return m;
+}
+
+/* Cluster shift of the cluster whose minimum is root (Sec. II.D, step 4):
+ * pick(word 0 of Philox(root, t, 0, SWF), q), a NULL draw shifts by 0. */
+int32_t ocvf_sw_shift(const ocvf_params *p, uint32_t root, uint32_t t)
+{
+    uint32_t w[4];
+    philox(root, t, 0, OCVF_SWF, p->seed, w);
+    int32_t r = ocvf_pick(w[0], (uint32_t)p->q);
+    return r < 0 ? 0 : r;
+}
+
 static void sw_step(ocvf_state *s)
 {
     const int32_t L = s->p.L, q = s->p.q;
     const int64_t N = s->N;
     uint8_t *sg = s->sigma;
-    double Jeff = s->p.J - s->p.P * s->p.vHB;
-    uint64_t thr_sigma = s->sw[0];
-    uint64_t thr_eff = s->sw[1 + s->theta];
     for (int64_t c = 0; c < N; ++c) {
-        uint32_t w0[4], w1[4], w[8];
-        philox((uint32_t)c, (uint32_t)s->t, 0, OCVF_SWB, s->p.seed, w0);
-        philox((uint32_t)c, (uint32_t)s->t, 1, OCVF_SWB, s->p.seed, w1);
-        for (int i = 0; i < 4; ++i) { w[i] = w0[i]; w[4 + i] = w1[i]; }
-        uint8_t m = 0;
-        for (int l = 0; l < 2; ++l) {
-            int a = 2 * l;                                   /* arm 0 or 2 */
-            int eq = sg[a * N + c] == sg[(a + 1) * N + nb(L, c, a)];
-            int bond = 0;
-            if (s->theta == 1) {
-                if (Jeff > 0.0) bond = eq && (uint64_t)w[l] < thr_eff;
-                else if (Jeff < 0.0) bond = !eq && (uint64_t)w[l] < thr_eff;
-            }
-            if (bond) m |= (uint8_t)(1u << l);
-        }
-        for (int l = 0; l < 6; ++l) {
-            int eq = sg[pair_a[l] * N + c] == sg[pair_b[l] * N + c];
-            if (eq && (uint64_t)w[2 + l] < thr_sigma) m |= (uint8_t)(1u << (2 + l));
-        }
-        s->mask[c] = m;
+        uint8_t s4[4];
+        for (int a = 0; a < 4; ++a) s4[a] = sg[a * N + c];
+        s->mask[c] = ocvf_sw_cell_mask(&s->p, s->sw, s->theta, c, (uint32_t)s->t, s4, sg[1 * N + nb(L, c, 0)],
+                                       sg[3 * N + nb(L, c, 2)]);
     }
     ocvf_components(L, s->mask, s->label);
-    for (int64_t idx = 0; idx < 4 * N; ++idx) {
-        uint32_t w[4];
-        philox(s->label[idx], (uint32_t)s->t, 0, OCVF_SWF, s->p.seed, w);
-        int32_t r = ocvf_pick(w[0], (uint32_t)q);
-        if (r < 0) r = 0;
-        sg[idx] = (uint8_t)((sg[idx] + r) % q);
-    }
+    for (int64_t idx = 0; idx < 4 * N; ++idx)
+        sg[idx] = (uint8_t)((sg[idx] + ocvf_sw_shift(&s->p, s->label[idx], (uint32_t)s->t)) % q);
     count(s, &s->n_hb_raw, &s->n_coop, NULL);
 }
 

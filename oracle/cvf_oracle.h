@@ -74,6 +74,15 @@ void     ocvf_tables(const ocvf_params *p, uint32_t met[2][3][7], uint64_t sw[3]
 /* connected components of the sigma graph defined by a per-cell bond mask */
 void     ocvf_components(int32_t L, const uint8_t *mask, uint32_t *label);
 
+/* one cell (the sweeps are built from these; also usable on sampled cells of
+ * lattices too large for a full oracle run) */
+void     ocvf_init_cell(const ocvf_params *p, int64_t c, uint8_t s4[4]);
+void     ocvf_met_cell(const ocvf_params *p, const uint32_t tab[3][7], int64_t c, uint32_t t, uint8_t s4[4],
+                       const uint8_t f4[4], int64_t *d_hb, int64_t *d_coop, int64_t *n_acc);
+uint8_t  ocvf_sw_cell_mask(const ocvf_params *p, const uint64_t sw[3], int32_t theta, int64_t c, uint32_t t,
+                           const uint8_t s4[4], uint8_t f0, uint8_t f2);
+int32_t  ocvf_sw_shift(const ocvf_params *p, uint32_t root, uint32_t t);
+
 /* Markov chain */
 ocvf_state *ocvf_create(const ocvf_params *p);
 void     ocvf_destroy(ocvf_state *s);
