@@ -129,20 +129,12 @@ __device__ __forceinline__ SwBondCtx sw_ctx(const LatticeArgs& a)
     return k;
 }
 
-// Bond activation of cell c: the 8-bit link mask (also stored in mask[c]).
-// f0o, f2o: the (old) sigma of the arms facing arm 0 and arm 2 of c.
-__device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwBondCtx& k, uint32_t c, uint32_t x,
-                                                 uint32_t y, int& f0o, int& f2o)
+// Bond activation of cell c (link mask): s0..s3 its bond indices, f0 / f2
+// the facing arms of its arms 0 and 2 (arm 1 of the +x neighbour, arm 3 of
+// the +y neighbour).
+__device__ __forceinline__ uint32_t sw_bond_bits(const LatticeArgs& a, const SwBondCtx& k, uint32_t c, uint32_t s0,
+                                                 uint32_t s1, uint32_t s2, uint32_t s3, uint32_t f0, uint32_t f2)
 {
-    const uint32_t L = a.L;
-    const size_t N = a.N;
-    const uint8_t* __restrict__ s = a.sigma;
-    const uint32_t row = y * L;
-    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-    const uint32_t rp = (y + 1 == L) ? 0 : row + L;
-    const int s0 = s[c], s1 = s[N + c], s2 = s[2 * N + c], s3 = s[3 * N + c];
-    const int f0 = s[N + xp + row];
-    const int f2 = s[3 * N + x + rp];
     const uint4 w0 = philox(c, k.t, 0u, kStreamSwb, a.key0, a.key1);
     const uint4 w1 = philox(c, k.t, 1u, kStreamSwb, a.key0, a.key1);
     uint32_t m = 0;
@@ -158,9 +150,6 @@ __device__ __forceinline__ uint32_t sw_bond_mask(const LatticeArgs& a, const SwB
     m |= (s1 == s2 && below(w1.y, k.thr_s)) ? 32u : 0u;
     m |= (s1 == s3 && below(w1.z, k.thr_s)) ? 64u : 0u;
     m |= (s2 == s3 && below(w1.w, k.thr_s)) ? 128u : 0u;
-    a.mask[c] = (uint8_t)m;
-    f0o = f0;
-    f2o = f2;
     return m;
 }
 
@@ -336,17 +325,29 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     const SwBondCtx k = sw_ctx(a);
     const uint32_t L = a.L, N = a.N;
     uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
+    // cell i of a thread: tile column lane, tile row wave + 4 i (wave-uniform),
+    // so plane and row offsets are scalar and the loads need no vector address
+    const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool col_in = lane < g.w;
+    const uint32_t x = g.x0 + lane;
+    const uint32_t vx = col_in ? x : 0u, vxp = col_in ? ((x + 1 == L) ? 0u : x + 1) : 0u;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N), rm = buf_rsrc(a.mask, N);
     uint32_t mk[kTC / 256];
 #pragma unroll
     for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+        const uint32_t ly = wave + 4 * i;
         uint32_t m = 0;
-        if (lx < g.w && ly < g.h) {
-            const uint32_t x = g.x0 + lx, y = g.y0 + ly;
-            int f0, f2;
-            m = sw_bond_mask(a, k, x + y * L, x, y, f0, f2);
-            if (lx == g.w - 1) edge[ly] = (uint8_t)f0;
-            if (ly == g.h - 1) edge[kTH + lx] = (uint8_t)f2;
+        if (ly < g.h) {
+            const uint32_t y = g.y0 + ly, row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
+            const uint32_t s0 = ld8(rs, vx, row), s1 = ld8(rs, vx, N + row), s2 = ld8(rs, vx, 2 * N + row),
+                           s3 = ld8(rs, vx, 3 * N + row);
+            const uint32_t f0 = ld8(rs, vxp, N + row), f2 = ld8(rs, vx, 3 * N + rowp);
+            if (col_in) {
+                m = sw_bond_bits(a, k, x + row, s0, s1, s2, s3, f0, f2);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)m, rm, (int)vx, (int)row, 0);
+                if (lane == g.w - 1) edge[ly] = (uint8_t)f0;
+                if (ly == g.h - 1) edge[kTH + lane] = (uint8_t)f2;
+            }
         }
         mk[i] = m;
     }
@@ -356,9 +357,7 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     __builtin_amdgcn_s_setprio(0);
     // every bond index: its tile-local root (| flag); flagged roots: a
     // global self-label; border bond indices: a global label of their root
-    const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool col_in = lane < g.w;
-    const uint32_t voff = col_in ? 2 * (g.x0 + lane) : 0u;
+    const uint32_t voff = 2 * vx;
 #pragma unroll
     for (uint32_t p = 0; p < 4; ++p) {
         const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
