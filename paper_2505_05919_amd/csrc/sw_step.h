@@ -187,6 +187,10 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 //  sw_labels_kernel       the full label array, on request.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kIdx = 0x0FFFu;     // local index bits of an LDS label
+#ifndef CVF_FLIP_JW
+#define CVF_FLIP_JW 4
+#endif
+constexpr int kJW = CVF_FLIP_JW;       // flip jobs per thread whose root chains are walked together
 constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
 
 struct TileGeom {
@@ -518,15 +522,16 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     }
     __syncthreads();
     // Jobs: one shift per component root, then the facing arms across the
-    // right edge (rows p < kTH) and the bottom edge (columns p - kTH).  Four
-    // jobs per thread at a time, their root chains followed in lockstep.
+    // right edge (rows p < kTH) and the bottom edge (columns p - kTH).  kJW
+    // jobs per thread at a time, their root chains followed in lockstep (one
+    // memory round trip per step for all of them).
     const uint32_t nr = nroot, njobs = nr + kEdgeBytes;
     const uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
-    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += 4 * 256) {
-        uint32_t x[4], dst[4];
-        bool chase[4], live[4];
+    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += kJW * 256) {
+        uint32_t x[kJW], dst[kJW];
+        bool chase[kJW], live[kJW];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kJW; ++k) {
             const uint32_t j = j0 + 256 * k;
             live[k] = j < njobs;
             chase[k] = false;
@@ -553,19 +558,23 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
                 if (!live[k]) x[k] = 0;
             }
         }
-        while (chase[0] || chase[1] || chase[2] || chase[3]) {
-            uint32_t pn[4];
+        for (;;) {
+            bool any = false;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) pn[k] = a.label[chase[k] ? x[k] : 0u];
+            for (int k = 0; k < kJW; ++k) any = any || chase[k];
+            if (!any) break;
+            uint32_t pn[kJW];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < kJW; ++k) pn[k] = a.label[chase[k] ? x[k] : 0u];
+#pragma unroll
+            for (int k = 0; k < kJW; ++k)
                 if (chase[k]) {
                     if (pn[k] == x[k]) chase[k] = false;
                     else x[k] = pn[k];
                 }
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kJW; ++k) {
             if (!live[k]) continue;
             const uint32_t w = philox(x[k], t, 0u, kStreamSwf, a.key0, a.key1).x;
             const uint32_t sft = (w <= a.flip_lim) ? (uint32_t)((double)w * a.flip_invd) : 0u;
