@@ -277,29 +277,49 @@ __device__ __forceinline__ void unite_lds(uint32_t* lab, uint32_t a, uint32_t b)
 }
 
 // In-tile components from the link masks mk[i] of cells lc = tid + 256 i:
-// the in-cell components (LUT), then the covalent links inside the tile;
+// the in-cell components (LUT) and the +x links of each row (ballots), then
+// the +y links inside the tile (lock-free union-find in LDS);
 // finally the roots of components holding a border bond index get kBorder.
 // The minimum-index root does not depend on the order of the unions, so
 // every kernel that rebuilds the components from the same mask gets the
 // same roots.  Expects lut ready; ends with a barrier.
 __device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_t (&mk)[kTC / 256], const TileGeom& g)
 {
+    const uint32_t lane = threadIdx.x & 63;                // = tile column: a wavefront holds a tile row
 #pragma unroll
     for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i;
-        const uint32_t l4 = lut[mk[i] >> 2];
-        lab[lc] = (l4 & 3) * kTC + lc;
-        lab[kTC + lc] = ((l4 >> 2) & 3) * kTC + lc;
+        const uint32_t lc = threadIdx.x + 256 * i, ly = lc / kTW;
+        const uint32_t m = mk[i];
+        const uint32_t l4 = lut[m >> 2];
+        const uint32_t r1 = (l4 >> 2) & 3;                 // arm 0 is always its own in-cell root
+        // +x links inside the row: a run of cells joined arm 0 -> arm 1 of the
+        // next cell, continued through every cell whose arms 0 and 1 share an
+        // in-cell component, is one component whose minimum is arm 0 of the
+        // run's first cell.  Found with two ballots; no atomics.
+        const uint64_t lnk = __ballot((m & 1) && lane + 1 < g.w);
+        const bool in = lane > 0 && ((lnk >> (lane - 1)) & 1);
+        const uint64_t brk = __ballot(!(in && r1 == 0));  // bit j: a run starts at column j
+        uint32_t e0 = lc;
+        uint32_t b_root = 0;
+        if (in) {
+            const uint64_t upto = lane == 63 ? brk : (brk & ((2ull << lane) - 1));
+            const uint64_t before = brk & ((1ull << lane) - 1);
+            const uint32_t start = 63 - (uint32_t)__builtin_clzll(upto);
+            const uint32_t start_prev = 63 - (uint32_t)__builtin_clzll(before);
+            e0 = ly * kTW + start;                         // this cell's arm 0, if the run goes through
+            b_root = ly * kTW + start_prev;                // the run that reaches this cell's arm 1
+        }
+        lab[lc] = e0;
+        lab[kTC + lc] = r1 * kTC + lc;
         lab[2 * kTC + lc] = ((l4 >> 4) & 3) * kTC + lc;
         lab[3 * kTC + lc] = ((l4 >> 6) & 3) * kTC + lc;
+        if (in && r1 != 0) lab[r1 * kTC + lc] = b_root;    // arm 1's own component joins the run
     }
     __syncthreads();
 #pragma unroll
     for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
-        const uint32_t m = mk[i];
-        if ((m & 1) && lx + 1 < g.w) unite_lds(lab, lc, kTC + lc + 1);
-        if ((m & 2) && ly + 1 < g.h) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
+        const uint32_t lc = threadIdx.x + 256 * i, ly = lc / kTW;
+        if ((mk[i] & 2) && ly + 1 < g.h) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
     }
     __syncthreads();
     if (threadIdx.x < 2 * (kTW + kTH)) {
