@@ -412,19 +412,6 @@ __global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
     sw_tile_body(a, grid_tile(a.L), lut, lab);
 }
 
-// Roots of u and v with both chains followed in lockstep: one memory round
-// trip per step for the pair.  pu, pv: label[u], label[v], already loaded.
-__device__ __forceinline__ void find_roots2(const uint32_t* label, uint32_t& u, uint32_t& v, uint32_t pu,
-                                            uint32_t pv)
-{
-    while (pu != u || pv != v) {
-        u = pu;
-        v = pv;
-        pu = label[u];
-        pv = label[v];
-    }
-}
-
 // Covalent links that leave their tile: +x links of the last column of each
 // tile (and of column L-1, which wraps), +y links of the last row of each
 // tile (and of row L-1).  Thread i < L * ncx handles column-edge cells,
@@ -453,23 +440,24 @@ __device__ __forceinline__ void sw_edge_body(const LatticeArgs& a, uint32_t i, u
         bit = 2;
     }
     const uint32_t m = a.mask[c];
-    const uint32_t pu = a.label[u], pv = a.label[v];
+    uint32_t pu = a.label[u], pv = a.label[v];
     if (!(m & bit)) return;
-    find_roots2(a.label, u, v, pu, pv);
-    // Lock-free union by minimum index: atomicMin points the larger root at the
-    // smaller.  A failed attempt means the larger root got a parent meanwhile;
-    // the union continues from that parent, so no connection is lost, and the
-    // larger of the two roots strictly decreases each round.
-    while (u != v) {
-        if (u > v) {
-            const uint32_t tmp = u;
-            u = v;
-            v = tmp;
+    // Lock-free union by minimum index without root finding: both ends start
+    // from their tile roots (usually still roots), and atomicMin points the
+    // larger node of the pair at the smaller one.  It returns the node's
+    // previous parent p: p == node means it was a root and the union is done;
+    // otherwise the node now points at min(p, smaller) and the pair (smaller,
+    // p) is united next, so no connection is lost.  The larger element of the
+    // pair strictly decreases, so the loop ends.
+    while (pu != pv) {
+        if (pu > pv) {
+            const uint32_t tmp = pu;
+            pu = pv;
+            pv = tmp;
         }
-        const uint32_t old = atomicMin(a.label + v, u);
-        if (old == v) return;
-        v = old;                           // v got a parent meanwhile: unite from there
-        find_roots2(a.label, u, v, a.label[u], a.label[v]);
+        const uint32_t old = atomicMin(a.label + pv, pu);
+        if (old == pv) return;
+        pv = old;
     }
 }
 
