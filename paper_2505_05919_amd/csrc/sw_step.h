@@ -468,11 +468,14 @@ __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint
 }
 
 // LDS of the flip: the compacted component roots (| kBorder), whose space
-// then holds the new sigma of the tile; the shift of each root; the new
-// sigma facing the right / bottom edge; the root count.
+// then holds the new sigma of the tile; the shift of each root; the old (then
+// new) sigma of the tile, kept here rather than in registers so that the
+// kernel fits 8 wavefronts per SIMD; the new sigma facing the right / bottom
+// edge; the root count.
 struct FlipLds {
     uint16_t roots[4 * kTC];
     uint8_t sh[4 * kTC];
+    uint8_t osg[4 * kTC];
     uint8_t across[kEdgeBytes];
     uint32_t nroot;
 };
@@ -507,6 +510,8 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
             if (col_in) lr[i] = l;
         }
     }
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
     // component roots, compacted: one LDS atomic per wavefront (the ballots
     // are taken twice rather than kept: 16 of them would not fit in SGPRs)
     auto is_root = [&](uint32_t i) {
@@ -599,15 +604,15 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
         const uint32_t ly = ent_row(wave, i);
-        uint32_t s = os[i] + sh[lr[i] & kIdx];
+        uint32_t s = lds.osg[ent_local(wave, lane, i)] + sh[lr[i] & kIdx];
         s = s >= q ? s - q : s;
         if (col_in && ly < g.h)
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)s, rs, (int)voff, (int)((i >> 2) * N + (g.y0 + ly) * L), 0);
-        os[i] = s;
+        lds.osg[ent_local(wave, lane, i)] = (uint8_t)s;
     }
     __syncthreads();                          // the root list is dead: its space holds the new sigma
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) nsg[ent_local(wave, lane, i)] = (uint8_t)os[i];
+    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) nsg[ent_local(wave, lane, i)] = lds.osg[ent_local(wave, lane, i)];
     __syncthreads();
     // recount of the new configuration: the +x and +y HB pairs and the six
     // in-cell pairs of every cell of the tile
@@ -627,7 +632,7 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     block_add<2>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
 }
 
-__global__ __launch_bounds__(256) void sw_flip_tile_kernel(LatticeArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
 {
     if (a.st->skip) return;
     __shared__ FlipLds lds;
@@ -703,7 +708,7 @@ __global__ __launch_bounds__(256) void sw_edge_batch_kernel(const BatchEntry* __
     sw_edge_body(a, (blockIdx.x - estart[c]) * 256 + threadIdx.x, ncx, ncy);
 }
 
-__global__ __launch_bounds__(256) void sw_flip_batch_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_batch_kernel(
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ tstart, uint32_t count)
 {
     __shared__ FlipLds lds;
