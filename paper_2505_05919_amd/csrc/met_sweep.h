@@ -29,8 +29,8 @@ __device__ __forceinline__ void met_arm(uint32_t& s4, uint32_t Z, uint32_t prop,
     // M in {3, 5} divides 2^32 - 1 and needs prop' = prop + 1 (prop = 2^32-1 is the
     // NULL proposal); M in {1, 2, 4} divides 2^32 and has no NULL proposal.
     constexpr bool kHasNull = (M == 3 || M == 5);
-    const uint32_t pp = kHasNull ? prop + 1u : prop;
-    uint32_t kp = (uint32_t)(((uint64_t)pp * M + (1ull << 32)) >> 32);
+    // (prop + 1) M + 2^32 = prop M + (2^32 + M): the +1 folds into the addend
+    uint32_t kp = (uint32_t)(((uint64_t)prop * M + ((1ull << 32) + (kHasNull ? M : 0u))) >> 32);
     // Empty asm, no instruction: kp stays a 32-bit value, so that 4 kp + s4 is
     // one v_lshl_add_u32 instead of a 64-bit shift folded into alignbit + and.
     __asm__("" : "+v"(kp));
@@ -39,7 +39,7 @@ __device__ __forceinline__ void met_arm(uint32_t& s4, uint32_t Z, uint32_t prop,
     const int d = (int)__builtin_amdgcn_ubfe(Z, sn4, 4) - (int)__builtin_amdgcn_ubfe(Z, s4, 4);
     const uint2 e = tbl[d + 16];
     bool acc = min(accw, 0xFFFFFFFEu) < e.x;              // thr == 2^32-1 always accepts
-    if (kHasNull) acc = acc && pp != 0u;
+    if (kHasNull) acc = acc && prop != 0xFFFFFFFFu;       // the NULL proposal
     s4 = acc ? sn4 : s4;
     wsum += acc ? e.y : 0u;
 }
