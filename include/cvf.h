@@ -168,10 +168,10 @@ int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
  * launches and their mean duration in ms since timing was enabled. */
 #define CVF_K_VOLUME    0   /* volume move / counter fold          */
 #define CVF_K_MET_SWEEP 1   /* one checkerboard colour sweep       */
-#define CVF_K_SW_BONDS  2   /* bond activation + in-cell labels    */
-#define CVF_K_SW_UNION  3   /* covalent unions                     */
-#define CVF_K_SW_FLIP   4   /* flatten + cluster flip              */
-#define CVF_K_RECOUNT   5   /* lattice recount                     */
+#define CVF_K_SW_BONDS  2   /* bond activation + in-tile labels    */
+#define CVF_K_SW_UNION  3   /* tile-crossing covalent unions       */
+#define CVF_K_SW_FLIP   4   /* cluster shift + recount             */
+#define CVF_K_RECOUNT   5   /* lattice recount (separate launches) */
 #define CVF_K_COUNT     6
 int cvf_timing_enable(cvf_state *st, int enable);
 int cvf_kernel_times(cvf_state *st, int kind, int64_t *launches, double *mean_ms);

@@ -1,7 +1,7 @@
 // Swendsen-Wang step kernels and the lattice recount (included inside the
-// kernels' namespace).  Every kernel body is a per-cell function; the
-// single-chain kernels loop over cells grid-stride, the batched kernels run one
-// cell per thread for the chain their workgroup belongs to.
+// kernels' namespace).  The step kernels work on 64 x 16-cell tiles; each
+// has a body shared by the single-chain kernel (grid = the chain's tiles) and
+// the batched kernel (workgroup -> chain and tile through prefix sums).
 #pragma once
 
 // ---------------------------------------------------------------------------
