@@ -109,7 +109,7 @@ int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
 /* Device workspace needed for the algorithms in algo_mask: Metropolis
  * needs a few KB; Swendsen-Wang adds 25 bytes per cell (uint32 labels and
  * uint16 tile-local roots of the 4N bond indices, one bond mask byte per
- * cell) and 80 bytes per 64 x 16-cell tile.  Host only. */
+ * cell) and 96 bytes per 64 x 32-cell tile.  Host only. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
 /* Create a chain.  d_sigma: 4*L*L bytes of device memory, layout above;

@@ -23,7 +23,11 @@ constexpr int kSlots = 256;
 // or column is ragged).  Per tile the bond kernel keeps, for the step's
 // fused recount, the old sigma of the facing arm across the right edge (kTH
 // bytes, one per row) and across the bottom edge (kTW bytes, one per column).
-constexpr uint32_t kTW = 64, kTH = 16, kTC = kTW * kTH;
+#ifndef CVF_SW_TILE_H
+#define CVF_SW_TILE_H 32
+#endif
+constexpr uint32_t kTW = 64, kTH = CVF_SW_TILE_H, kTC = kTW * kTH;
+constexpr uint32_t kTT = kTC / 4;        // threads of a tile workgroup: 4 cells, 16 bond indices each
 constexpr uint32_t kEdgeBytes = kTW + kTH;
 
 // Mutable per-chain scalars, at offset 0 of the workspace.

@@ -44,10 +44,10 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 
 // Sum NV int32 values over the workgroup and add them (as int64) to
 // dst[i * stride] (one atomic per value per workgroup).
-template <int NV>
+template <int NV, int BLOCK = kBlock>
 __device__ __forceinline__ void block_add(const int (&v)[NV], int64_t* dst, int stride)
 {
-    __shared__ int part[NV][kBlock / 64];
+    __shared__ int part[NV][BLOCK / 64];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -59,7 +59,7 @@ __device__ __forceinline__ void block_add(const int (&v)[NV], int64_t* dst, int 
     if (tid < NV) {
         int64_t s = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += part[tid][w];
+        for (int w = 0; w < BLOCK / 64; ++w) s += part[tid][w];
         if (s) atomicAdd((unsigned long long*)(dst + (size_t)tid * stride), (unsigned long long)s);
     }
 }
@@ -376,7 +376,7 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
 hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_tile_kernel<<<grid, 256, 0, s>>>(a);
+    sw_tile_kernel<<<grid, kTT, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -419,23 +419,23 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_
                            int stage, hipStream_t s)
 {
     if (total_blocks == 0) return hipSuccess;
-    if (stage == 0) sw_tile_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
+    if (stage == 0) sw_tile_batch_kernel<<<total_blocks, kTT, 0, s>>>(ent, start, count);
     else if (stage == 1) sw_edge_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
-    else sw_flip_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
+    else sw_flip_batch_kernel<<<total_blocks, kTT, 0, s>>>(ent, start, count);
     return hipGetLastError();
 }
 
 hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_flip_tile_kernel<<<grid, 256, 0, s>>>(a);
+    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_labels_kernel<<<grid, 256, 0, s>>>(a, out);
+    sw_labels_kernel<<<grid, kTT, 0, s>>>(a, out);
     return hipGetLastError();
 }
 

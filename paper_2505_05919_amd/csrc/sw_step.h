@@ -1,5 +1,5 @@
 // Swendsen-Wang step kernels and the lattice recount (included inside the
-// kernels' namespace).  The step kernels work on 64 x 16-cell tiles; each
+// kernels' namespace).  The step kernels work on kTW x kTH-cell tiles; each
 // has a body shared by the single-chain kernel (grid = the chain's tiles) and
 // the batched kernel (workgroup -> chain and tile through prefix sums).
 #pragma once
@@ -166,7 +166,8 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 }
 
 // ---------------------------------------------------------------------------
-// Tiled Swendsen-Wang step.  A workgroup owns a tile of kTW x kTH cells, i.e.
+// Tiled Swendsen-Wang step.  A workgroup of kTT threads owns a tile of kTW x
+// kTH cells, i.e.
 // 4 kTC bond indices with local index v = arm * kTC + ly * kTW + lx, whose
 // order is the order of the global flat indices arm * N + y * L + x.
 //  sw_tile_kernel         bonds of the tile's cells (mask) and the in-tile
@@ -186,12 +187,16 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 //                         configuration.
 //  sw_labels_kernel       the full label array, on request.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kIdx = 0x0FFFu;     // local index bits of an LDS label
+constexpr uint32_t kIdx = 4 * kTC - 1;  // local index bits of an LDS label
 #ifndef CVF_FLIP_JW
 #define CVF_FLIP_JW 4
 #endif
 constexpr int kJW = CVF_FLIP_JW;       // flip jobs per thread whose root chains are walked together
 constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
+static_assert(4 * kTC <= kBorder, "local bond indices must stay below the border flag");
+static_assert(kTT >= 2 * (kTW + kTH), "one thread per border bond index");
+static_assert(kTW == 64, "a wavefront holds one tile row");
+static_assert(4 * (kTT / 64) == kTH, "four rows per wavefront cover the tile");
 
 struct TileGeom {
     uint32_t x0, y0, w, h, id;
@@ -224,9 +229,11 @@ __device__ __forceinline__ uint32_t tile_global(const TileGeom& g, uint32_t L, u
     return (v / kTC) * N + (g.y0 + lc / kTW) * L + g.x0 + lc % kTW;
 }
 
-// The 4 kTC / 256 = 16 bond indices of a thread: entry i lies in plane i / 4,
-// tile row wave + 4 (i % 4) (wave-uniform) and tile column lane.
-__device__ __forceinline__ uint32_t ent_row(uint32_t wave, uint32_t i) { return wave + 4 * (i & 3); }
+// The 4 kTC / kTT = 16 bond indices of a thread: entry i lies in plane i / 4,
+// tile row wave + W (i % 4) (wave-uniform; W = kTT / 64 wavefronts, so the
+// four rows of a wavefront cover the kTH = 4 W rows of the tile) and tile
+// column lane.
+__device__ __forceinline__ uint32_t ent_row(uint32_t wave, uint32_t i) { return wave + (kTT / 64) * (i & 3); }
 __device__ __forceinline__ uint32_t ent_local(uint32_t wave, uint32_t lane, uint32_t i)
 {
     return (i >> 2) * kTC + ent_row(wave, i) * kTW + lane;
@@ -276,19 +283,19 @@ __device__ __forceinline__ void unite_lds(uint32_t* lab, uint32_t a, uint32_t b)
     }
 }
 
-// In-tile components from the link masks mk[i] of cells lc = tid + 256 i:
+// In-tile components from the link masks mk[i] of cells lc = tid + kTT i:
 // the in-cell components (LUT) and the +x links of each row (ballots), then
 // the +y links inside the tile (lock-free union-find in LDS);
 // finally the roots of components holding a border bond index get kBorder.
 // The minimum-index root does not depend on the order of the unions, so
 // every kernel that rebuilds the components from the same mask gets the
 // same roots.  Expects lut ready; ends with a barrier.
-__device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_t (&mk)[kTC / 256], const TileGeom& g)
+__device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_t (&mk)[kTC / kTT], const TileGeom& g)
 {
     const uint32_t lane = threadIdx.x & 63;                // = tile column: a wavefront holds a tile row
 #pragma unroll
-    for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, ly = lc / kTW;
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t lc = threadIdx.x + kTT * i, ly = lc / kTW;
         const uint32_t m = mk[i];
         const uint32_t l4 = lut[m >> 2];
         const uint32_t r1 = (l4 >> 2) & 3;                 // arm 0 is always its own in-cell root
@@ -317,8 +324,8 @@ __device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_
     }
     __syncthreads();
 #pragma unroll
-    for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, ly = lc / kTW;
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t lc = threadIdx.x + kTT * i, ly = lc / kTW;
         if ((mk[i] & 2) && ly + 1 < g.h) unite_lds(lab, 2 * kTC + lc, 3 * kTC + lc + kTW);
     }
     __syncthreads();
@@ -329,11 +336,11 @@ __device__ void tile_components(uint32_t* lab, const uint8_t* lut, const uint32_
     __syncthreads();
 }
 
-__device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom& g, uint32_t (&mk)[kTC / 256])
+__device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom& g, uint32_t (&mk)[kTC / kTT])
 {
 #pragma unroll
-    for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t lc = threadIdx.x + kTT * i, lx = lc % kTW, ly = lc / kTW;
         mk[i] = (lx < g.w && ly < g.h) ? a.mask[(g.y0 + ly) * a.L + g.x0 + lx] : 0u;
     }
 }
@@ -349,17 +356,17 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     const SwBondCtx k = sw_ctx(a);
     const uint32_t L = a.L, N = a.N;
     uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
-    // cell i of a thread: tile column lane, tile row wave + 4 i (wave-uniform),
+    // cell i of a thread: tile column lane, tile row wave + W i (wave-uniform),
     // so plane and row offsets are scalar and the loads need no vector address
     const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool col_in = lane < g.w;
     const uint32_t x = g.x0 + lane;
     const uint32_t vx = col_in ? x : 0u, vxp = col_in ? ((x + 1 == L) ? 0u : x + 1) : 0u;
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N), rm = buf_rsrc(a.mask, N);
-    uint32_t mk[kTC / 256];
+    uint32_t mk[kTC / kTT];
 #pragma unroll
-    for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t ly = wave + 4 * i;
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t ly = wave + (kTT / 64) * i;
         uint32_t m = 0;
         if (ly < g.h) {
             const uint32_t y = g.y0 + ly, row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
@@ -387,7 +394,7 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
         const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
 #pragma unroll 2
         for (uint32_t k = 0; k < 4; ++k) {
-            const uint32_t ly = wave + 4 * k;
+            const uint32_t ly = ent_row(wave, k);
             if (ly >= g.h) break;
             const uint32_t v = p * kTC + ly * kTW + lane;
             const uint32_t r = find_root_lds(lab, v);
@@ -404,7 +411,7 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     }
 }
 
-__global__ __launch_bounds__(256) void sw_tile_kernel(LatticeArgs a)
+__global__ __launch_bounds__(kTT) void sw_tile_kernel(LatticeArgs a)
 {
     if (a.st->skip) return;
     __shared__ uint8_t lut[64];
@@ -491,14 +498,14 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     const uint32_t L = a.L, N = a.N, q = a.q;
     const uint32_t t = a.st->t_cur;
     if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
-    // entry i: plane i / 4, tile row wave + 4 (i % 4), column lane
+    // entry i: plane i / 4, tile row ent_row(wave, i), column lane
     const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool col_in = lane < g.w;
     const uint32_t voff = col_in ? g.x0 + lane : 0u;
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N);
-    uint32_t os[4 * kTC / 256], lr[4 * kTC / 256];     // old sigma, local root | kBorder
+    uint32_t os[4 * kTC / kTT], lr[4 * kTC / kTT];     // old sigma, local root | kBorder
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
         const uint32_t p = i >> 2, ly = ent_row(wave, i);
         os[i] = 0;
         lr[i] = ent_local(wave, lane, i);
@@ -511,7 +518,7 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
         }
     }
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
     // component roots, compacted: one LDS atomic per wavefront (the ballots
     // are taken twice rather than kept: 16 of them would not fit in SGPRs)
     auto is_root = [&](uint32_t i) {
@@ -519,13 +526,13 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     };
     uint32_t cnt = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) cnt += (uint32_t)__popcll(__ballot(is_root(i)));
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) cnt += (uint32_t)__popcll(__ballot(is_root(i)));
     __syncthreads();                          // nroot = 0
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&nroot, cnt);
     base = (uint32_t)__shfl((int)base, 0);
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
         const bool root = is_root(i);
         const uint64_t bal = __ballot(root);
         const uint32_t pos =
@@ -540,12 +547,12 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     // memory round trip per step for all of them).
     const uint32_t nr = nroot, njobs = nr + kEdgeBytes;
     const uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
-    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += kJW * 256) {
+    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += kJW * kTT) {
         uint32_t x[kJW], dst[kJW];
         bool chase[kJW], live[kJW];
 #pragma unroll
         for (int k = 0; k < kJW; ++k) {
-            const uint32_t j = j0 + 256 * k;
+            const uint32_t j = j0 + kTT * k;
             live[k] = j < njobs;
             chase[k] = false;
             x[k] = 0;
@@ -602,7 +609,7 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     }
     __syncthreads();
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
         const uint32_t ly = ent_row(wave, i);
         uint32_t s = lds.osg[ent_local(wave, lane, i)] + sh[lr[i] & kIdx];
         s = s >= q ? s - q : s;
@@ -612,14 +619,14 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     }
     __syncthreads();                          // the root list is dead: its space holds the new sigma
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) nsg[ent_local(wave, lane, i)] = lds.osg[ent_local(wave, lane, i)];
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) nsg[ent_local(wave, lane, i)] = lds.osg[ent_local(wave, lane, i)];
     __syncthreads();
     // recount of the new configuration: the +x and +y HB pairs and the six
     // in-cell pairs of every cell of the tile
     int hb = 0, co = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kTC / 256; ++i) {
-        const uint32_t lc = threadIdx.x + 256 * i, lx = lc % kTW, ly = lc / kTW;
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t lc = threadIdx.x + kTT * i, lx = lc % kTW, ly = lc / kTW;
         if (lx < g.w && ly < g.h) {
             const uint32_t s0 = nsg[lc], s1 = nsg[kTC + lc], s2 = nsg[2 * kTC + lc], s3 = nsg[3 * kTC + lc];
             const uint32_t f0 = lx + 1 < g.w ? nsg[kTC + lc + 1] : across[ly];
@@ -629,10 +636,10 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
         }
     }
     const int v2[2] = {hb, co};
-    block_add<2>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
+    block_add<2, kTT>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
 {
     if (a.st->skip) return;
     __shared__ FlipLds lds;
@@ -642,20 +649,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // label[idx] = the minimum of idx's cluster, for every bond index; written
 // to out (4N uint32).  Works from the mask and the global labels left by
 // either the tiled or the batched step.
-__global__ __launch_bounds__(256) void sw_labels_kernel(LatticeArgs a, uint32_t* __restrict__ out)
+__global__ __launch_bounds__(kTT) void sw_labels_kernel(LatticeArgs a, uint32_t* __restrict__ out)
 {
     __shared__ uint8_t lut[64];
     __shared__ uint32_t lab[4 * kTC];
     build_incell_lut(lut);
     const uint32_t L = a.L, N = a.N;
     const TileGeom g = grid_tile(L);
-    uint32_t mk[kTC / 256];
+    uint32_t mk[kTC / kTT];
     tile_masks(a, g, mk);
     __syncthreads();
     tile_components(lab, lut, mk, g);
 #pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / 256; ++i) {
-        const uint32_t v = threadIdx.x + 256 * i;
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
+        const uint32_t v = threadIdx.x + kTT * i;
         if (!tile_in(g, v)) continue;
         const uint32_t r = find_root_lds(lab, v);
         const uint32_t gr = tile_global(g, L, N, r);
@@ -687,7 +694,7 @@ __device__ __forceinline__ TileGeom batch_tile(const LatticeArgs& a, uint32_t lo
     return tile_geom(a.L, local - by * ncx, by, ncx);
 }
 
-__global__ __launch_bounds__(256) void sw_tile_batch_kernel(const BatchEntry* __restrict__ ent,
+__global__ __launch_bounds__(kTT) void sw_tile_batch_kernel(const BatchEntry* __restrict__ ent,
                                                             const uint32_t* __restrict__ tstart, uint32_t count)
 {
     __shared__ uint8_t lut[64];
@@ -708,7 +715,7 @@ __global__ __launch_bounds__(256) void sw_edge_batch_kernel(const BatchEntry* __
     sw_edge_body(a, (blockIdx.x - estart[c]) * 256 + threadIdx.x, ncx, ncy);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_batch_kernel(
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_batch_kernel(
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ tstart, uint32_t count)
 {
     __shared__ FlipLds lds;

@@ -48,11 +48,11 @@ def test_workspace_bytes(cvf):
     met = cvf.cvf_workspace_bytes(p, cvf.CVF_ALGO_METROPOLIS)
     both = cvf.cvf_workspace_bytes(p, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
     N = 1414 * 1414
-    tiles = ((1414 + 63) // 64) * ((1414 + 15) // 16)
+    tiles = ((1414 + 63) // 64) * ((1414 + 31) // 32)
     assert met < 8192
-    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell, 80 B per 64x16 tile
-    assert both - met >= 25 * N + 80 * tiles
-    assert both - met < 25 * N + 80 * tiles + 1024
+    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell, 96 B per 64x32 tile
+    assert both - met >= 25 * N + 96 * tiles
+    assert both - met < 25 * N + 96 * tiles + 1024
 
 
 @pytest.mark.parametrize("field,value", [("L", 3), ("L", 0), ("L", 32768), ("q", 1), ("q", 7),
