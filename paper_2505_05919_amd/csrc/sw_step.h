@@ -194,6 +194,7 @@ constexpr uint32_t kIdx = 4 * kTC - 1;  // local index bits of an LDS label
 constexpr int kJW = CVF_FLIP_JW;       // flip jobs per thread whose root chains are walked together
 constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
 static_assert(4 * kTC <= kBorder, "local bond indices must stay below the border flag");
+static_assert((4 * kTC & (4 * kTC - 1)) == 0, "kIdx is a bit mask");
 static_assert(kTT >= 2 * (kTW + kTH), "one thread per border bond index");
 static_assert(kTW == 64, "a wavefront holds one tile row");
 static_assert(4 * (kTT / 64) == kTH, "four rows per wavefront cover the tile");
@@ -387,21 +388,38 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     tile_components(lab, lut, mk, g);
     __builtin_amdgcn_s_setprio(0);
     // every bond index: its tile-local root (| flag); flagged roots: a
-    // global self-label; border bond indices: a global label of their root
+    // global self-label; border bond indices: a global label of their root.
+    // Eight bond indices at a time: their parents, then the parents' entries
+    // (a root's entry is the root | flag, so nearly every index is settled by
+    // these two reads); the few longer chains are followed in lockstep.
+    // Rows past a ragged tile's end hold singletons and are read, not stored.
     const uint32_t voff = 2 * vx;
 #pragma unroll
-    for (uint32_t p = 0; p < 4; ++p) {
-        const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
-#pragma unroll 2
-        for (uint32_t k = 0; k < 4; ++k) {
-            const uint32_t ly = ent_row(wave, k);
-            if (ly >= g.h) break;
-            const uint32_t v = p * kTC + ly * kTW + lane;
-            const uint32_t r = find_root_lds(lab, v);
-            const uint32_t flag = lab[r] & kBorder;
-            if (col_in) {
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(r | flag), rl, (int)voff, (int)(2 * (g.y0 + ly) * L), 0);
-                if (r == v && flag) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, v);
+    for (uint32_t h = 0; h < 2; ++h) {
+        uint32_t r[8], e[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) r[j] = lab[(2 * h + (j >> 2)) * kTC + (j & 3) * kTT + threadIdx.x] & kIdx;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) e[j] = lab[r[j]];
+        for (;;) {
+            bool more = false;
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) more = more || (e[j] & kIdx) != r[j];
+            if (!more) break;
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) {
+                r[j] = e[j] & kIdx;                    // unchanged where already settled
+                e[j] = lab[r[j]];
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            const uint32_t p = 2 * h + (j >> 2), ly = ent_row(wave, j & 3);
+            if (ly < g.h && col_in) {
+                const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)e[j], rl, (int)voff, (int)(2 * (g.y0 + ly) * L), 0);
+                const uint32_t v = p * kTC + ly * kTW + lane;
+                if (r[j] == v && (e[j] & kBorder)) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, v);
             }
         }
     }
