@@ -188,14 +188,11 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 //  sw_labels_kernel       the full label array, on request.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kIdx = 4 * kTC - 1;  // local index bits of an LDS label
-#ifndef CVF_FLIP_JW
-#define CVF_FLIP_JW 4
-#endif
-constexpr int kJW = CVF_FLIP_JW;       // flip jobs per thread whose root chains are walked together
+constexpr uint32_t kBorderIdx = 2 * (kTW + kTH);   // border bond indices of a tile
 constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
 static_assert(4 * kTC <= kBorder, "local bond indices must stay below the border flag");
 static_assert((4 * kTC & (4 * kTC - 1)) == 0, "kIdx is a bit mask");
-static_assert(kTT >= 2 * (kTW + kTH), "one thread per border bond index");
+static_assert(kTT >= kBorderIdx + kEdgeBytes, "one flip thread per border component and facing arm");
 static_assert(kTW == 64, "a wavefront holds one tile row");
 static_assert(4 * (kTT / 64) == kTH, "four rows per wavefront cover the tile");
 
@@ -492,27 +489,47 @@ __global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint
     sw_edge_body(a, blockIdx.x * 256 + threadIdx.x, ncx, ncy);
 }
 
-// LDS of the flip: the compacted component roots (| kBorder), whose space
-// then holds the new sigma of the tile; the shift of each root; the old (then
-// new) sigma of the tile, kept here rather than in registers so that the
-// kernel fits 8 wavefronts per SIMD; the new sigma facing the right / bottom
-// edge; the root count.
+// LDS of the flip: the compacted roots of the interior components, whose
+// space then holds the new sigma of the tile; the shift of each root; the
+// old (then new) sigma of the tile, kept here rather than in registers so
+// that the kernel fits 8 wavefronts per SIMD; the compacted roots of the
+// border components (at most one per border bond index); the new sigma
+// facing the right / bottom edge; the two root counts.
 struct FlipLds {
     uint16_t roots[4 * kTC];
     uint8_t sh[4 * kTC];
     uint8_t osg[4 * kTC];
+    uint16_t rootb[kBorderIdx];
     uint8_t across[kEdgeBytes];
-    uint32_t nroot;
+    uint32_t nroot, nrootb;
 };
+
+// Exclusive prefix sum over the wavefront of per-lane values c < 32, and
+// its total: one ballot per bit.
+__device__ __forceinline__ uint32_t wave_excl_scan5(uint32_t c, uint32_t& total)
+{
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 5; ++b) {
+        const uint64_t m = __ballot((c >> b) & 1u);
+        pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+        tot += (uint32_t)__popcll(m) << b;
+    }
+    total = tot;
+    return pre;
+}
 
 __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeom& g, FlipLds& lds)
 {
     uint16_t* roots = lds.roots;
     uint8_t* sh = lds.sh;
     uint8_t* across = lds.across;
-    uint32_t& nroot = lds.nroot;
+    uint16_t* rootb = lds.rootb;
     uint8_t* nsg = reinterpret_cast<uint8_t*>(roots);
-    if (threadIdx.x == 0) nroot = 0;
+    if (threadIdx.x == 0) {
+        lds.nroot = 0;
+        lds.nrootb = 0;
+    }
     const uint32_t L = a.L, N = a.N, q = a.q;
     const uint32_t t = a.st->t_cur;
     if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
@@ -537,92 +554,87 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     }
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
-    // component roots, compacted: one LDS atomic per wavefront (the ballots
-    // are taken twice rather than kept: 16 of them would not fit in SGPRs)
+    // component roots, compacted into an interior and a border list: a lane's
+    // slots follow from a prefix sum of the per-lane counts over the
+    // wavefront, one LDS atomic per wavefront and list places the wavefront
+    // (the order of a list is immaterial: every entry sets its own root's
+    // shift)
     auto is_root = [&](uint32_t i) {
         return col_in && ent_row(wave, i) < g.h && (lr[i] & kIdx) == ent_local(wave, lane, i);
     };
-    uint32_t cnt = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) cnt += (uint32_t)__popcll(__ballot(is_root(i)));
-    __syncthreads();                          // nroot = 0
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&nroot, cnt);
-    base = (uint32_t)__shfl((int)base, 0);
+    uint32_t cnt = 0, cntb = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
-        const bool root = is_root(i);
-        const uint64_t bal = __ballot(root);
-        const uint32_t pos =
-            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (root) roots[pos] = (uint16_t)lr[i];
-        base += (uint32_t)__popcll(bal);
+        const bool root = is_root(i), border = (lr[i] & kBorder) != 0;
+        cnt += (root && !border) ? 1u : 0u;
+        cntb += (root && border) ? 1u : 0u;
+    }
+    uint32_t tot, totb;
+    uint32_t pos = wave_excl_scan5(cnt, tot), posb = wave_excl_scan5(cntb, totb);
+    __syncthreads();                          // counts = 0
+    uint32_t base = 0, baseb = 0;
+    if (lane == 0) {
+        base = atomicAdd(&lds.nroot, tot);
+        baseb = atomicAdd(&lds.nrootb, totb);
+    }
+    pos += (uint32_t)__shfl((int)base, 0);
+    posb += (uint32_t)__shfl((int)baseb, 0);
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
+        const bool root = is_root(i), border = (lr[i] & kBorder) != 0;
+        if (root && !border) roots[pos++] = (uint16_t)lr[i];
+        if (root && border) {
+            if (posb < kBorderIdx) rootb[posb] = (uint16_t)(lr[i] & kIdx);
+            ++posb;
+        }
     }
     __syncthreads();
-    // Jobs: one shift per component root, then the facing arms across the
-    // right edge (rows p < kTH) and the bottom edge (columns p - kTH).  kJW
-    // jobs per thread at a time, their root chains followed in lockstep (one
-    // memory round trip per step for all of them).
-    const uint32_t nr = nroot, njobs = nr + kEdgeBytes;
+    // One shift per component, drawn at its cluster minimum.  Border
+    // components and the facing arms across the right edge (p < kTH) and
+    // the bottom edge (column p - kTH) need the global root chain: one job
+    // per thread, whose first link is loaded before the interior components
+    // (whose minimum is their own root) are drawn, so that the load's
+    // latency is hidden behind that arithmetic.
+    const uint32_t nr = lds.nroot, nb = min(lds.nrootb, kBorderIdx);
     const uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
-    for (uint32_t j0 = threadIdx.x; j0 < njobs; j0 += kJW * kTT) {
-        uint32_t x[kJW], dst[kJW];
-        bool chase[kJW], live[kJW];
-#pragma unroll
-        for (int k = 0; k < kJW; ++k) {
-            const uint32_t j = j0 + kTT * k;
-            live[k] = j < njobs;
-            chase[k] = false;
-            x[k] = 0;
-            dst[k] = 0;
-            if (j < nr) {
-                const uint32_t e = roots[j];
-                dst[k] = e & kIdx;
-                x[k] = tile_global(g, L, N, e & kIdx);
-                chase[k] = (e & kBorder) != 0;
-            } else if (live[k]) {
-                const uint32_t p = j - nr;
-                dst[k] = 0x10000u | p;
-                if (p < kTH) {
-                    live[k] = p < g.h;
-                    const uint32_t xx = g.x0 + g.w - 1, yy = g.y0 + p;
-                    x[k] = N + ((xx + 1 == L) ? 0 : xx + 1) + yy * L;
-                } else {
-                    live[k] = p - kTH < g.w;
-                    const uint32_t xx = g.x0 + (p - kTH), yy = g.y0 + g.h - 1;
-                    x[k] = 3 * N + xx + ((yy + 1 == L) ? 0 : yy + 1) * L;
-                }
-                chase[k] = live[k];
-                if (!live[k]) x[k] = 0;
-            }
+    uint32_t x = 0, dst = 0;
+    bool live = false;
+    if (threadIdx.x < nb) {
+        dst = rootb[threadIdx.x];
+        x = tile_global(g, L, N, dst);
+        live = true;
+    } else if (threadIdx.x - nb < kEdgeBytes) {
+        const uint32_t p = threadIdx.x - nb;
+        dst = 0x10000u | p;
+        if (p < kTH) {
+            live = p < g.h;
+            const uint32_t xx = g.x0 + g.w - 1, yy = g.y0 + p;
+            x = N + ((xx + 1 == L) ? 0 : xx + 1) + yy * L;
+        } else {
+            live = p - kTH < g.w;
+            const uint32_t xx = g.x0 + (p - kTH), yy = g.y0 + g.h - 1;
+            x = 3 * N + xx + ((yy + 1 == L) ? 0 : yy + 1) * L;
         }
-        for (;;) {
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < kJW; ++k) any = any || chase[k];
-            if (!any) break;
-            uint32_t pn[kJW];
-#pragma unroll
-            for (int k = 0; k < kJW; ++k) pn[k] = a.label[chase[k] ? x[k] : 0u];
-#pragma unroll
-            for (int k = 0; k < kJW; ++k)
-                if (chase[k]) {
-                    if (pn[k] == x[k]) chase[k] = false;
-                    else x[k] = pn[k];
-                }
+    }
+    uint32_t pn = live ? a.label[x] : 0u;
+    for (uint32_t j = threadIdx.x; j < nr; j += kTT) {
+        const uint32_t e = roots[j];
+        const uint32_t w = philox(tile_global(g, L, N, e), t, 0u, kStreamSwf, a.key0, a.key1).x;
+        sh[e] = (uint8_t)((w <= a.flip_lim) ? (uint32_t)((double)w * a.flip_invd) : 0u);
+    }
+    if (live) {
+        while (pn != x) {
+            x = pn;
+            pn = a.label[x];
         }
-#pragma unroll
-        for (int k = 0; k < kJW; ++k) {
-            if (!live[k]) continue;
-            const uint32_t w = philox(x[k], t, 0u, kStreamSwf, a.key0, a.key1).x;
-            const uint32_t sft = (w <= a.flip_lim) ? (uint32_t)((double)w * a.flip_invd) : 0u;
-            if (dst[k] < 0x10000u) {
-                sh[dst[k]] = (uint8_t)sft;
-            } else {
-                const uint32_t p = dst[k] & 0xFFFFu;
-                const uint32_t s = edge[p] + sft;
-                across[p] = (uint8_t)(s >= q ? s - q : s);
-            }
+        const uint32_t w = philox(x, t, 0u, kStreamSwf, a.key0, a.key1).x;
+        const uint32_t sft = (w <= a.flip_lim) ? (uint32_t)((double)w * a.flip_invd) : 0u;
+        if (dst < 0x10000u) {
+            sh[dst] = (uint8_t)sft;
+        } else {
+            const uint32_t p = dst & 0xFFFFu;
+            const uint32_t s = edge[p] + sft;
+            across[p] = (uint8_t)(s >= q ? s - q : s);
         }
     }
     __syncthreads();
