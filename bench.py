@@ -33,7 +33,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # decision (14)
 ALU_OPS_PER_UPDATE = 34
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "met_colour_L4096_counters.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "met_sweep.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "met_sweep.h", "met_launch.h")]
 
 
 def log(*a):

@@ -8,17 +8,10 @@
 #include <vector>
 
 #include "cvf_internal.h"
+#include "met_launch.h"
 
 using namespace cvf;
 
-// Target number of wavefronts of a Metropolis colour launch.
-#ifndef CVF_MET_WAVES
-#define CVF_MET_WAVES 8192
-#endif
-// Use the dword (4-column) Metropolis kernel when L % 4 == 0.
-#ifndef CVF_MET_QUAD
-#define CVF_MET_QUAD 1
-#endif
 
 struct cvf_state {
     cvf_params p;
@@ -246,21 +239,11 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     a.jeff_sign = Jeff > 0.0 ? 1 : (Jeff < 0.0 ? -1 : 0);
     a.met_invd = 1.0 / (double)dm;
     a.flip_invd = 1.0 / (double)dq;
-    // Metropolis launch shape: lanes own column pairs (64 per wave), each wave
-    // walks `rows` rows; aim for CVF_MET_WAVES waves in the grid.
     {
-        a.quad = (a.L % 4 == 0) ? CVF_MET_QUAD : 0;
-        const uint32_t per_lane = a.quad ? 4 : 2;           // columns owned by a lane
-        const uint32_t groups = (a.L / per_lane + 63) / 64;
-        const uint32_t target = CVF_MET_WAVES;
-        const uint32_t waves_per_group = groups >= target ? 1 : target / groups;
-        uint32_t rows = (a.L + waves_per_group - 1) / waves_per_group;
-        rows = (rows + 1) & ~1u;
-        if (rows < 2) rows = 2;
-        if (rows > 32) rows = 32;
-        const uint32_t segs = (a.L + rows - 1) / rows;
-        a.rows = rows;
-        a.row_blocks = (segs + 3) / 4;
+        const MetShape m = met_shape(a.L);
+        a.quad = m.quad;
+        a.rows = m.rows;
+        a.row_blocks = m.row_blocks;
     }
 
     VolArgs& v = st->va;
@@ -438,17 +421,6 @@ size_t batch_layout(int32_t count, size_t* off_start, size_t* off_tstart, size_t
     return ent + 3 * st;
 }
 
-uint32_t met_rows_for(uint32_t L, uint32_t quad, uint32_t target_waves)
-{
-    const uint32_t per_lane = quad ? 4 : 2;
-    const uint32_t groups = (L / per_lane + 63) / 64;
-    const uint32_t waves_per_group = groups >= target_waves ? 1 : target_waves / groups;
-    uint32_t rows = (L + waves_per_group - 1) / waves_per_group;
-    rows = (rows + 1) & ~1u;
-    if (rows < 2) rows = 2;
-    if (rows > 32) rows = 32;
-    return rows;
-}
 
 void drop_graph(cvf_batch* b)
 {

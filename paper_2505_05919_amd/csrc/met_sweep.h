@@ -307,10 +307,10 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     return wsum;
 }
 
-// No occupancy cap: the quad loop needs ~80 VGPRs (6 wavefronts per SIMD).
-// Capping it at 64 VGPRs for 8 wavefronts spills to scratch and measured
-// slower; with the progress priority the 2048-workgroup grid runs as one full
-// round plus a short second one.
+// No occupancy cap: the quad loop needs ~84 VGPRs (5 wavefronts per SIMD).
+// Caps measured slower (64 VGPRs for 7 wavefronts without spills, or 8 with
+// a small spill).  At L = 4096 the host picks 16 rows per wavefront: 1024
+// workgroups, all resident at once.
 template <int Q, int KAPPA>
 __global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
 {
