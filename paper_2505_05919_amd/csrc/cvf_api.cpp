@@ -442,6 +442,14 @@ int batch_upload(cvf_batch* b, hipStream_t s)
         BatchEntry& e = b->host[c];
         memset(&e, 0, sizeof(e));
         e.la = st->la;
+        if (e.la.quad == 2) {
+            // column pairs in batches: small lattices get twice the
+            // wavefronts (measured faster on the 256-replica mix)
+            const MetShape m = met_shape_mode(e.la.L, 0);
+            e.la.quad = m.quad;
+            e.la.rows = m.rows;
+            e.la.row_blocks = m.row_blocks;
+        }
         if (b->rows > 0) {
             const uint32_t segs = (e.la.L + b->rows - 1) / (uint32_t)b->rows;
             e.la.rows = (uint32_t)b->rows;
@@ -451,7 +459,7 @@ int batch_upload(cvf_batch* b, hipStream_t s)
         e.va.mode = kVolMet;
         e.va.met_att_add = 4 * (int64_t)st->N;
         const uint32_t per_lane = e.la.quad ? 4 : 2;
-        e.groups_x = (e.la.L / per_lane + 63) / 64;
+        e.groups_x = ((e.la.L + per_lane - 1) / per_lane + 63) / 64;
         e.blocks = e.groups_x * e.la.row_blocks;
         b->start[c] = total;
         total += e.blocks;

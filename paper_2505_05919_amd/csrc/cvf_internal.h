@@ -90,7 +90,7 @@ struct LatticeArgs {
     double flip_invd;        // 1 / floor(2^32/q)
     uint32_t rows;           // Metropolis: rows per wavefront (even, <= 32)
     uint32_t row_blocks;     // Metropolis: grid.y
-    uint32_t quad;           // Metropolis: 1 = dword (4-column) lanes, needs L % 4 == 0
+    uint32_t quad;           // Metropolis: 1 / 2 = dword (4-column) lanes, L % 4 == 0 / 2; 0 = column pairs
 };
 
 struct VolArgs {

@@ -301,17 +301,24 @@ hipError_t launch_volume(const VolArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int Q, bool R>
+void launch_quad_r(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
+{
+    if (colour == 0) met_sweep4_kernel<Q, 0, R><<<grid, 256, 0, s>>>(a);
+    else met_sweep4_kernel<Q, 1, R><<<grid, 256, 0, s>>>(a);
+}
+
 template <int Q>
 void launch_quad(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
 {
-    if (colour == 0) met_sweep4_kernel<Q, 0><<<grid, 256, 0, s>>>(a);
-    else met_sweep4_kernel<Q, 1><<<grid, 256, 0, s>>>(a);
+    if (a.quad == 2) launch_quad_r<Q, true>(a, colour, grid, s);
+    else launch_quad_r<Q, false>(a, colour, grid, s);
 }
 
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
 {
     if (a.quad) {
-        const dim3 grid((a.L / 4 + 63) / 64, a.row_blocks);
+        const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
         switch (a.q) {
         case 2: launch_quad<2>(a, colour, grid, s); break;
         case 3: launch_quad<3>(a, colour, grid, s); break;

@@ -112,13 +112,20 @@ __device__ __forceinline__ void met_cell(const LatticeArgs& a, __amdgpu_buffer_r
 }
 
 // ---------------------------------------------------------------------------
-// Quad variant (L % 4 == 0): lane j owns the four columns 4j..4j+3 and moves
-// whole dwords of every plane.  In a row of parity P the updated cells sit at
-// bytes P and P+2 of the quad; their x neighbours are the other bytes of the
-// same dwords except one, fetched with a single byte load (the column left of
-// the quad for P = 0, right of it for P = 1).  The two bytes of the other
-// colour are written back unchanged -- nothing writes them during this pass.
-// Per row and lane: 6 dword loads + 1 byte load + 4 dword stores for 2 cells.
+// Quad variant: lane j owns the four columns 4j..4j+3 and moves whole dwords
+// of every plane.  In a row of parity P the updated cells sit at bytes P and
+// P+2 of the quad; their x neighbours are the other bytes of the same dwords
+// except one, fetched with a single byte load (the column left of the quad
+// for P = 0, right of it for P = 1).  The two bytes of the other colour are
+// written back unchanged -- nothing writes them during this pass.  Per row
+// and lane: 6 dword loads + 1 byte load + 4 dword stores for 2 cells.
+// R (L % 4 == 2): plane offsets stay dword-aligned, even rows start on a
+// dword and odd rows two bytes past one, so the dwords of odd rows are moved
+// as two 16-bit halves.  The last quad of a row holds columns L-2, L-1 and
+// two phantom bytes (the next row's first columns, or in odd rows a second
+// copy of the low half): only its first cell is real, its +x neighbour for
+// P = 1 is the wrapped edge byte, the phantom cell's counter increments are
+// dropped, and only the low half is stored.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ld32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -130,26 +137,64 @@ __device__ __forceinline__ void st32(__amdgpu_buffer_rsrc_t r, uint32_t v, uint3
     __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
 }
 
+__device__ __forceinline__ void st16(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, (int)voff, (int)soff, 0);
+}
+
+// Dword of a row that starts two bytes past a dword boundary (MIS): two
+// 16-bit halves, the high one at voff_hi (voff + 2; voff for the last quad
+// of a row, whose high half is a phantom, so that no load leaves sigma).
+template <bool MIS>
+__device__ __forceinline__ uint32_t ld32r(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t voff_hi, uint32_t soff)
+{
+    if (!MIS) return ld32(r, voff, soff);
+    const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff_hi, (int)soff, 0);
+    return lo | (hi << 16);
+}
+
+// Store of a quad dword: whole, or (R) the low half only for the last quad
+// of a row, and as two halves in rows that start off a dword boundary.
+template <bool R, bool MIS>
+__device__ __forceinline__ void st32r(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff,
+                                      bool ragged)
+{
+    if (!R) {
+        st32(r, v, voff, soff);
+    } else if (MIS) {
+        st16(r, v, voff, soff);
+        if (!ragged) st16(r, v >> 16, voff + 2, soff);
+    } else if (ragged) {
+        st16(r, v, voff, soff);
+    } else {
+        st32(r, v, voff, soff);
+    }
+}
+
 struct QuadBytes {
     uint32_t d0, d1, d2, d3;   // arms 0..3 of the quad, row y
     uint32_t up3, dn2;         // arm 3 of row y+1, arm 2 of row y-1
     uint32_t edge;             // P=0: arm 0 of the column left of the quad; P=1: arm 1 right of it
 };
 
-template <int P>
+// ODD: y is odd.  With R the row of y is off a dword boundary when y is odd,
+// and its neighbour rows (y +- 1, wrapping to 0 or L-1) when y is even.
+template <int P, bool R, bool ODD>
 __device__ __forceinline__ QuadBytes met_load4(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, uint32_t y,
-                                               uint32_t x4, uint32_t xl, uint32_t xr)
+                                               uint32_t x4, uint32_t x4h, uint32_t xl, uint32_t xr)
 {
+    constexpr bool DMIS = R && ODD, NMIS = R && !ODD;
     const uint32_t L = a.L, N = a.N;
     const uint32_t yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
     const uint32_t o0 = y * L;
     QuadBytes q;
-    q.d0 = ld32(rs, x4, o0);
-    q.d1 = ld32(rs, x4, o0 + N);
-    q.d2 = ld32(rs, x4, o0 + 2 * N);
-    q.d3 = ld32(rs, x4, o0 + 3 * N);
-    q.up3 = ld32(rs, x4, 3 * N + yp * L);
-    q.dn2 = ld32(rs, x4, 2 * N + ym * L);
+    q.d0 = ld32r<DMIS>(rs, x4, x4h, o0);
+    q.d1 = ld32r<DMIS>(rs, x4, x4h, o0 + N);
+    q.d2 = ld32r<DMIS>(rs, x4, x4h, o0 + 2 * N);
+    q.d3 = ld32r<DMIS>(rs, x4, x4h, o0 + 3 * N);
+    q.up3 = ld32r<NMIS>(rs, x4, x4h, 3 * N + yp * L);
+    q.dn2 = ld32r<NMIS>(rs, x4, x4h, 2 * N + ym * L);
     q.edge = (P == 0) ? ld8(rs, xl, o0) : ld8(rs, xr, o0 + N);
     return q;
 }
@@ -170,9 +215,10 @@ __device__ __forceinline__ uint32_t put2(uint32_t d, uint32_t v1, uint32_t v2)
     return (d & keep) | w1 | (v2 << (8 * B2 - 2));
 }
 
-template <int Q, int P>
+template <int Q, int P, bool R, bool ODD>
 __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, const uint2* tbl,
-                                         uint32_t t, uint32_t y, uint32_t x4, const QuadBytes& q, uint32_t& wsum)
+                                         uint32_t t, uint32_t y, uint32_t x4, const QuadBytes& q, uint32_t& wsum,
+                                         bool ragged)
 {
     constexpr int B1 = P, B2 = P + 2;                 // bytes of the two updated cells
     const uint32_t N = a.N, o0 = y * a.L;
@@ -183,7 +229,7 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
     // cell at byte B2
     uint32_t b0 = byte4<B2>(D0), b1 = byte4<B2>(D1), b2 = byte4<B2>(D2), b3 = byte4<B2>(D3);
     {
-        const uint32_t f0 = byte4<B1 + 1>(D1);                          // arm 1, column +1
+        const uint32_t f0 = (R && P == 1 && ragged) ? E : byte4<B1 + 1>(D1);   // arm 1, column +1
         const uint32_t f1 = (P == 0) ? E : byte4<(B1 > 0 ? B1 - 1 : 0)>(D0);   // arm 0, column -1
         const uint32_t f2 = byte4<B1>(U3), f3 = byte4<B1>(M2);
         const uint32_t c = x4 + B1 + o0;
@@ -196,6 +242,7 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
         met_arm<Q>(a2, p01 + (1u << a3) + (8u << f2), wb.x, wb.y, tbl, wsum);
         met_arm<Q>(a3, p01 + (1u << a2) + (8u << f3), wb.z, wb.w, tbl, wsum);
     }
+    const uint32_t wkeep = wsum;                      // R: the last quad's second cell is a phantom
     {
         const uint32_t f0 = (P == 1) ? E : byte4<(B2 < 3 ? B2 + 1 : 3)>(D1);
         const uint32_t f1 = byte4<B2 - 1>(D0);
@@ -210,10 +257,12 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
         met_arm<Q>(b2, p01 + (1u << b3) + (8u << f2), wb.x, wb.y, tbl, wsum);
         met_arm<Q>(b3, p01 + (1u << b2) + (8u << f3), wb.z, wb.w, tbl, wsum);
     }
-    st32(rs, put2<B1, B2>(q.d0, a0, b0), x4, o0);
-    st32(rs, put2<B1, B2>(q.d1, a1, b1), x4, o0 + N);
-    st32(rs, put2<B1, B2>(q.d2, a2, b2), x4, o0 + 2 * N);
-    st32(rs, put2<B1, B2>(q.d3, a3, b3), x4, o0 + 3 * N);
+    if (R && ragged) wsum = wkeep;
+    constexpr bool DMIS = R && ODD;
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d0, a0, b0), x4, o0, ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d1, a1, b1), x4, o0 + N, ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d2, a2, b2), x4, o0 + 2 * N, ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d3, a3, b3), x4, o0 + 3 * N, ragged);
 }
 
 __device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int theta)
@@ -273,7 +322,7 @@ struct ProgressPrio {
 // (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  The first
 // row's loads are issued before the LDS table is built, so both latencies
 // overlap.  Returns the lane's packed counter sum.
-template <int Q, int KAPPA, bool PRIO>
+template <int Q, int KAPPA, bool PRIO, bool R>
 __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
                                                    uint32_t bx, uint32_t by)
 {
@@ -282,26 +331,28 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t j = bx * 64 + lane;
     const uint32_t y0 = (by * 4 + wave) * a.rows;      // even
-    const bool active = j < (L >> 2) && y0 < L;
+    const bool active = j < ((L + 3) >> 2) && y0 < L;   // (L + 2) / 4 quads when R
     const uint32_t x4 = 4 * j;
-    const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 == L) ? 0 : x4 + 4;
+    const bool ragged = R && x4 + 2 == L;
+    const uint32_t x4h = ragged ? x4 : x4 + 2;         // high halves of off-boundary rows
+    const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 >= L) ? 0 : x4 + 4;
     const uint32_t y1 = min(y0 + a.rows, L);
     const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
     // even rows: updated cells at bytes KAPPA, KAPPA+2; odd rows: 1-KAPPA, 3-KAPPA
     constexpr int PE = KAPPA, PO = 1 - KAPPA;
     QuadBytes cur = {};
-    if (active) cur = met_load4<PE>(a, rs, y0, x4, xl, xr);
+    if (active) cur = met_load4<PE, R, false>(a, rs, y0, x4, x4h, xl, xr);
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
     if (active) {
         const ProgressPrio<PRIO> prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
             prio.step((y - y0) >> 1);
-            const QuadBytes odd = met_load4<PO>(a, rs, y + 1, x4, xl, xr);
-            met_quad<Q, PE>(a, rs, tbl, t, y, x4, cur, wsum);
+            const QuadBytes odd = met_load4<PO, R, true>(a, rs, y + 1, x4, x4h, xl, xr);
+            met_quad<Q, PE, R, false>(a, rs, tbl, t, y, x4, cur, wsum, ragged);
             const uint32_t yn = (y + 2 < y1) ? y + 2 : y;
-            cur = met_load4<PE>(a, rs, yn, x4, xl, xr);
-            met_quad<Q, PO>(a, rs, tbl, t, y + 1, x4, odd, wsum);
+            cur = met_load4<PE, R, false>(a, rs, yn, x4, x4h, xl, xr);
+            met_quad<Q, PO, R, true>(a, rs, tbl, t, y + 1, x4, odd, wsum, ragged);
         }
     }
     return wsum;
@@ -311,14 +362,14 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
 // Caps measured slower (64 VGPRs for 7 wavefronts without spills, or 8 with
 // a small spill).  At L = 4096 the host picks 16 rows per wavefront: 1024
 // workgroups, all resident at once.
-template <int Q, int KAPPA>
+template <int Q, int KAPPA, bool R>
 __global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
 {
     const int skip = a.st->skip, theta = a.st->theta;
     const uint32_t t = a.st->t_cur;
     if (skip) return;                                      // step limit reached
     __shared__ uint2 tbl[32];
-    const uint32_t wsum = met_quad_block<Q, KAPPA, true>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
+    const uint32_t wsum = met_quad_block<Q, KAPPA, true, R>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
@@ -400,7 +451,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const uint32_t local = blockIdx.x - start[lo];
     const uint32_t gx = ent[lo].groups_x;
     const uint32_t by = local / gx, bx = local - by * gx;
-    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA, false>(a, tbl, t, theta, bx, by)
+    // (batches move L % 4 == 2 lattices in column pairs: quad is 0 or 1 here)
+    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA, false, false>(a, tbl, t, theta, bx, by)
                                  : met_byte_block<Q, false>(a, tbl, t, theta, KAPPA, bx, by);
     met_reduce(wsum, a.slots, local);
 }

@@ -6,7 +6,8 @@ Metropolis (no volume move, so a sweep needs no global count): a colour-0
 cell moves against its initial neighbours, a colour-1 cell against its
 neighbours after their colour-0 moves; both are rebuilt cell by cell from
 the oracle's initial configuration and compared bit for bit.  L = 32764
-runs the dword-quad kernel, L = 32766 the byte kernel.
+runs the dword-quad kernel, L = 32766 the quad kernel with a two-column last
+quad (L % 4 == 2) and, through a batch of one, the column-pair kernel.
 
 Swendsen-Wang: properties that hold at any size, on sampled bond indices:
 every label is a root (label[label[i]] == label[i]) not above its index; the
@@ -47,17 +48,22 @@ def nbr(L, x, y, a):
     return [((x + 1) % L, y), ((x - 1) % L, y), (x, (y + 1) % L), (x, (y - 1) % L)][a]
 
 
-@pytest.mark.parametrize("L", [32764, 32766])
-def test_metropolis_max_size_sampled(cvf, oracle_mod, L):
+@pytest.mark.parametrize("L,batched", [(32764, False), (32766, False), (32766, True)])
+def test_metropolis_max_size_sampled(cvf, oracle_mod, L, batched):
     import torch
-    say(f"case metropolis max size L={L}")
+    say(f"case metropolis max size L={L} batched={batched}")
     p = cvf.cvf_params_from_si(T_K, P_MPA, L=L, seed=SEED, flags=cvf.CVF_NO_VOLUME_MOVE)
     op = oracle_mod.params_from_si(T_K, P_MPA, L=L, seed=SEED, flags=oracle_mod.NO_VOLUME_MOVE)
     met, _ = oracle_mod.tables(op)
     tab = met[1 if op.v_init < 2.0 else 0]
     N = L * L
     ch = cvf.Chain(p, cvf.CVF_ALGO_METROPOLIS)
-    ch.metropolis(1)
+    if batched:
+        b = cvf.Batch([ch])
+        b.metropolis(1)
+        b.close()
+    else:
+        ch.metropolis(1)
     o = ch.obs()
     assert o["consistent"] == 1 and o["met_attempted"] == 4 * N
 

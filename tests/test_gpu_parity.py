@@ -95,7 +95,7 @@ def test_tables_parity(cvf, oracle_mod, T, P):
     ch.close()
 
 
-@pytest.mark.parametrize("L,n", [(2, 50), (4, 40), (6, 30), (64, 20), (66, 20), (130, 10), (256, 5), (1026, 2)])
+@pytest.mark.parametrize("L,n", [(2, 50), (4, 40), (6, 30), (64, 20), (66, 20), (130, 10), (256, 5), (1026, 2), (2046, 1)])
 def test_metropolis_parity(cvf, oracle_mod, L, n):
     op = oracle_mod.params_from_si(300.0, 0.1, L=L, seed=100 + L)
     run_pair(cvf, oracle_mod, op, [("met", 1), ("met", n)])
