@@ -8,10 +8,11 @@
 // couples to the other arms of c (J_sigma) and to arm a^1 of the neighbour
 // in direction a (J_eff), which has the other colour.
 //
-// Work layout: lane i of a wavefront owns the column pair (2i, 2i+1) and
-// walks `rows` consecutive rows; in every row exactly one of its two cells
-// has the colour being updated.  Row addresses are wave-uniform (SGPR base +
-// lane column), so the loop carries no vector address arithmetic.
+// Work layout: a lane of a wavefront owns a column quad (4j..4j+3: two cells
+// of the updated colour per row) or, for smaller L % 4 == 2 lattices and
+// batches, a column pair (2i, 2i+1: one cell per row), and walks `rows`
+// consecutive rows.  Row addresses are wave-uniform (SGPR base + lane
+// column), so the loop carries no vector address arithmetic.
 //
 // Energy bookkeeping without compares: bond indices are held as 4*sigma and
 // Z = sum_{b != a} 1 << 4 sigma_b  +  8 << 4 sigma_facing
