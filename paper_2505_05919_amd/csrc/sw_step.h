@@ -554,21 +554,28 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     }
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
+    // the 16-bit local roots, two per register for the rest of the kernel
+    uint32_t lrp[2 * kTC / kTT];
+#pragma unroll
+    for (uint32_t k = 0; k < 2 * kTC / kTT; ++k) lrp[k] = lr[2 * k] | (lr[2 * k + 1] << 16);
+    auto LR = [&](uint32_t i) { return (lrp[i >> 1] >> (16 * (i & 1))) & 0xFFFFu; };
     // component roots, compacted into an interior and a border list: a lane's
     // slots follow from a prefix sum of the per-lane counts over the
     // wavefront, one LDS atomic per wavefront and list places the wavefront
     // (the order of a list is immaterial: every entry sets its own root's
     // shift)
-    auto is_root = [&](uint32_t i) {
-        return col_in && ent_row(wave, i) < g.h && (lr[i] & kIdx) == ent_local(wave, lane, i);
-    };
-    uint32_t cnt = 0, cntb = 0;
+    // The lane's roots as bits of one register (bit i: entry i is an
+    // interior root, bit 16 + i: a border root), so that no per-entry lane
+    // masks stay live in SGPRs between the two passes.
+    static_assert(4 * kTC / kTT == 16, "16 entries per thread");
+    uint32_t rf = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
-        const bool root = is_root(i), border = (lr[i] & kBorder) != 0;
-        cnt += (root && !border) ? 1u : 0u;
-        cntb += (root && border) ? 1u : 0u;
+        const bool root = col_in && ent_row(wave, i) < g.h && (LR(i) & kIdx) == ent_local(wave, lane, i);
+        const uint32_t bit = ((LR(i) >> 11) & 16u) + i;   // the border flag (bit 15) selects bit 16 + i
+        rf |= (root ? 1u : 0u) << bit;
     }
+    const uint32_t cnt = (uint32_t)__popc(rf & 0xFFFFu), cntb = (uint32_t)__popc(rf >> 16);
     uint32_t tot, totb;
     uint32_t pos = wave_excl_scan5(cnt, tot), posb = wave_excl_scan5(cntb, totb);
     __syncthreads();                          // counts = 0
@@ -581,12 +588,11 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     posb += (uint32_t)__shfl((int)baseb, 0);
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
-        const bool root = is_root(i), border = (lr[i] & kBorder) != 0;
-        if (root && !border) roots[pos++] = (uint16_t)lr[i];
-        if (root && border) {
-            if (posb < kBorderIdx) rootb[posb] = (uint16_t)(lr[i] & kIdx);
-            ++posb;
-        }
+        const uint32_t bi = (rf >> i) & 1u, bb = (rf >> (16 + i)) & 1u;
+        if (bi) roots[pos] = (uint16_t)LR(i);
+        pos += bi;
+        if (bb && posb < kBorderIdx) rootb[posb] = (uint16_t)(LR(i) & kIdx);
+        posb += bb;
     }
     __syncthreads();
     // One shift per component, drawn at its cluster minimum.  Border
@@ -638,10 +644,15 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
         }
     }
     __syncthreads();
+    // Empty asm, no instruction: the masked roots are recomputed here from
+    // the packed registers instead of being kept live (and spilled) across
+    // the draws since the compaction.
+#pragma unroll
+    for (uint32_t k = 0; k < 2 * kTC / kTT; ++k) __asm__("" : "+v"(lrp[k]));
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) {
         const uint32_t ly = ent_row(wave, i);
-        uint32_t s = lds.osg[ent_local(wave, lane, i)] + sh[lr[i] & kIdx];
+        uint32_t s = lds.osg[ent_local(wave, lane, i)] + sh[LR(i) & kIdx];
         s = s >= q ? s - q : s;
         if (col_in && ly < g.h)
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)s, rs, (int)voff, (int)((i >> 2) * N + (g.y0 + ly) * L), 0);
