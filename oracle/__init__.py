@@ -89,10 +89,15 @@ def lib():
         L.ocvf_sw_cell_mask.restype = ctypes.c_uint8
         L.ocvf_sw_shift.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32]
         L.ocvf_sw_shift.restype = ctypes.c_int32
+        L.ocvf_domain_order.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32)]
+        L.ocvf_dom_arm.argtypes = [P, u32p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, u8p, ctypes.c_uint8,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64)]
         L.ocvf_create.argtypes = [P]
         L.ocvf_create.restype = ctypes.c_void_p
         L.ocvf_destroy.argtypes = [ctypes.c_void_p]
         L.ocvf_metropolis_sweeps.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.ocvf_metropolis_domain_sweeps.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.ocvf_sw_steps.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.ocvf_observables.argtypes = [ctypes.c_void_p, ctypes.POINTER(Obs)]
         L.ocvf_get_sigma.argtypes = [ctypes.c_void_p, u8p]
@@ -185,6 +190,24 @@ def sw_shift(p: Params, root: int, t: int) -> int:
     return int(lib().ocvf_sw_shift(ctypes.byref(p), root, t))
 
 
+def domain_order(p: Params, t: int) -> list:
+    """Arms of the four passes of the arm-domain sweep at step t."""
+    out = (ctypes.c_int32 * 4)()
+    lib().ocvf_domain_order(ctypes.byref(p), t, out)
+    return list(out)
+
+
+def dom_arm(p: Params, tab: np.ndarray, c: int, t: int, a: int, s4, facing: int):
+    """Arm-domain move of arm a of cell c at step t.  Returns (new s4, d_hb,
+    d_coop, accepted)."""
+    s = np.ascontiguousarray(np.asarray(s4, dtype=np.uint8)).copy()
+    tb = np.ascontiguousarray(np.asarray(tab, dtype=np.uint32))
+    dh, dc, na = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().ocvf_dom_arm(ctypes.byref(p), _ptr(tb, ctypes.c_uint32), c, t, a, _ptr(s, ctypes.c_uint8), facing,
+                       ctypes.byref(dh), ctypes.byref(dc), ctypes.byref(na))
+    return s, dh.value, dc.value, na.value
+
+
 def components(L: int, mask: np.ndarray) -> np.ndarray:
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     assert m.size == L * L
@@ -213,6 +236,10 @@ class Chain:
 
     def sw(self, n: int):
         lib().ocvf_sw_steps(self._s, n)
+        return self
+
+    def metropolis_domain(self, n: int):
+        lib().ocvf_metropolis_domain_sweeps(self._s, n)
         return self
 
     def obs(self) -> dict:

@@ -293,34 +293,42 @@ static void volume_move(ocvf_state *s)
  * of the neighbour in direction a -- of the other colour, so fixed while the
  * cell moves), tab the acceptance table of the current theta.  Adds the
  * accepted changes of N_HB_raw and N_sigma and the acceptance count. */
+/* One Metropolis move of arm a of a cell: proposal word prop, acceptance
+ * word accw, s4 the cell's four bond indices, facing the bond index its arm
+ * a faces. */
+static void met_move(const ocvf_params *p, const uint32_t tab[3][7], int a, uint32_t prop, uint32_t accw,
+                     uint8_t s4[4], int32_t facing, int64_t *d_hb, int64_t *d_coop, int64_t *n_acc)
+{
+    const int32_t q = p->q;
+    int32_t k = ocvf_pick(prop, (uint32_t)(q - 1));
+    if (k < 0) return;                             /* null move */
+    int32_t old = s4[a];
+    int32_t neu = (old + 1 + k) % q;
+    int32_t dh = (neu == facing) - (old == facing);
+    int32_t dc = 0;
+    for (int b = 0; b < 4; ++b) {
+        if (b == a) continue;
+        int32_t sb = s4[b];
+        dc += (neu == sb) - (old == sb);
+    }
+    uint32_t thr = tab[dh + 1][dc + 3];
+    if (thr == 0xFFFFFFFFu || accw < thr) {
+        s4[a] = (uint8_t)neu;
+        *d_hb += dh;
+        *d_coop += dc;
+        ++*n_acc;
+    }
+}
+
 void ocvf_met_cell(const ocvf_params *p, const uint32_t tab[3][7], int64_t c, uint32_t t, uint8_t s4[4],
                    const uint8_t f4[4], int64_t *d_hb, int64_t *d_coop, int64_t *n_acc)
 {
-    const int32_t q = p->q;
     for (int a = 0; a < 4; ++a) {
         uint32_t w[4];
         philox((uint32_t)c, t, (uint32_t)(a >> 1), OCVF_MET, p->seed, w);
         uint32_t prop = (a & 1) ? w[2] : w[0];
         uint32_t accw = (a & 1) ? w[3] : w[1];
-        int32_t k = ocvf_pick(prop, (uint32_t)(q - 1));
-        if (k < 0) continue;                       /* null move */
-        int32_t old = s4[a];
-        int32_t neu = (old + 1 + k) % q;
-        int32_t facing = f4[a];
-        int32_t dh = (neu == facing) - (old == facing);
-        int32_t dc = 0;
-        for (int b = 0; b < 4; ++b) {
-            if (b == a) continue;
-            int32_t sb = s4[b];
-            dc += (neu == sb) - (old == sb);
-        }
-        uint32_t thr = tab[dh + 1][dc + 3];
-        if (thr == 0xFFFFFFFFu || accw < thr) {
-            s4[a] = (uint8_t)neu;
-            *d_hb += dh;
-            *d_coop += dc;
-            ++*n_acc;
-        }
+        met_move(p, tab, a, prop, accw, s4, f4[a], d_hb, d_coop, n_acc);
     }
 }
 
@@ -353,6 +361,78 @@ void ocvf_metropolis_sweeps(ocvf_state *s, int64_t n)
     for (int64_t i = 0; i < n; ++i) {
         volume_move(s);
         metropolis_sweep(s);
+        s->t++;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Arm-domain Metropolis sweep: the paper's own partition (Sec. II.C and its */
+/* figure of layered domains), in 2-D.  Arm a of every cell forms a domain:  */
+/* a bond index of arm a interacts with the three other arms of its cell and */
+/* with arm a^1 of the neighbour in direction a, none of them in the domain, */
+/* so a whole domain moves at once -- for any L, odd included.  A sweep is   */
+/* four passes, one per domain.  The paper picks the arm of each pass at     */
+/* random; reading: a uniform random permutation per sweep, so that every    */
+/* bond index moves once per sweep, drawn by Fisher-Yates from the words of  */
+/* Philox(0, t, 0, ORD) (position i swaps with i + pick(w_i, 4 - i); NONE,   */
+/* possible only for w_1 = 2^32 - 1, leaves position 1 in place).            */
+/* Words of arm a of cell (x, y) at step t: Philox(b, t, a, DOM) with        */
+/* b = floor(x/2) + ceil(L/2) y (one block per column pair of a row), words  */
+/* 0, 1 (proposal, acceptance) for even x and 2, 3 for odd x.                */
+/* ------------------------------------------------------------------------ */
+void ocvf_domain_order(const ocvf_params *p, uint32_t t, int32_t order[4])
+{
+    uint32_t w[4];
+    philox(0, t, 0, OCVF_ORD, p->seed, w);
+    for (int i = 0; i < 4; ++i) order[i] = i;
+    for (int i = 0; i < 3; ++i) {
+        int32_t k = ocvf_pick(w[i], (uint32_t)(4 - i));
+        if (k < 0) k = 0;
+        int32_t tmp = order[i];
+        order[i] = order[i + k];
+        order[i + k] = tmp;
+    }
+}
+
+void ocvf_dom_arm(const ocvf_params *p, const uint32_t tab[3][7], int64_t c, uint32_t t, int32_t a,
+                  uint8_t s4[4], uint8_t facing, int64_t *d_hb, int64_t *d_coop, int64_t *n_acc)
+{
+    const int64_t L = p->L, x = c % L, y = c / L;
+    uint32_t w[4];
+    philox((uint32_t)((x >> 1) + ((L + 1) >> 1) * y), t, (uint32_t)a, OCVF_DOM, p->seed, w);
+    uint32_t prop = (x & 1) ? w[2] : w[0];
+    uint32_t accw = (x & 1) ? w[3] : w[1];
+    met_move(p, tab, a, prop, accw, s4, facing, d_hb, d_coop, n_acc);
+}
+
+static void domain_sweep(ocvf_state *s)
+{
+    const int32_t L = s->p.L;
+    const int64_t N = s->N;
+    uint8_t *sg = s->sigma;
+    int32_t order[4];
+    ocvf_domain_order(&s->p, (uint32_t)s->t, order);
+    for (int k = 0; k < 4; ++k) {
+        const int a = order[k];
+        /* the domain's bond indices do not interact: updating them one after
+         * another in place equals updating them all at once */
+        for (int64_t c = 0; c < N; ++c) {
+            uint8_t s4[4];
+            for (int b = 0; b < 4; ++b) s4[b] = sg[b * N + c];
+            uint8_t f = sg[(a ^ 1) * N + nb(L, c, a)];
+            ocvf_dom_arm(&s->p, s->met[s->theta], c, (uint32_t)s->t, a, s4, f, &s->n_hb_raw, &s->n_coop,
+                         &s->met_acc);
+            sg[a * N + c] = s4[a];
+        }
+        s->met_att += N;
+    }
+}
+
+void ocvf_metropolis_domain_sweeps(ocvf_state *s, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        volume_move(s);
+        domain_sweep(s);
         s->t++;
     }
 }

@@ -27,14 +27,14 @@ extern "C" {
 #endif
 
 /* Philox stream identifiers (fourth counter word). */
-enum { OCVF_INIT = 0, OCVF_VOL = 1, OCVF_MET = 2, OCVF_SWB = 3, OCVF_SWF = 4 };
+enum { OCVF_INIT = 0, OCVF_VOL = 1, OCVF_MET = 2, OCVF_SWB = 3, OCVF_SWF = 4, OCVF_ORD = 5, OCVF_DOM = 6 };
 
 /* flags */
 #define OCVF_NO_VOLUME_MOVE 1u
 
 /* Reduced-unit parameters: energies in eps, volumes in v0 = r0^3. */
 typedef struct {
-    int32_t  L;        /* even, >= 2 */
+    int32_t  L;        /* >= 2 (the checkerboard sweep and SW need it even) */
     int32_t  q;        /* 2..6 */
     double   beta;     /* 1 / T*  */
     double   J;        /* covalent HB energy (Table I: 4*0.5)       */
@@ -82,11 +82,16 @@ void     ocvf_met_cell(const ocvf_params *p, const uint32_t tab[3][7], int64_t c
 uint8_t  ocvf_sw_cell_mask(const ocvf_params *p, const uint64_t sw[3], int32_t theta, int64_t c, uint32_t t,
                            const uint8_t s4[4], uint8_t f0, uint8_t f2);
 int32_t  ocvf_sw_shift(const ocvf_params *p, uint32_t root, uint32_t t);
+/* arm-domain sweep: pass order of step t, and one move of arm a of cell c */
+void     ocvf_domain_order(const ocvf_params *p, uint32_t t, int32_t order[4]);
+void     ocvf_dom_arm(const ocvf_params *p, const uint32_t tab[3][7], int64_t c, uint32_t t, int32_t a,
+                      uint8_t s4[4], uint8_t facing, int64_t *d_hb, int64_t *d_coop, int64_t *n_acc);
 
 /* Markov chain */
 ocvf_state *ocvf_create(const ocvf_params *p);
 void     ocvf_destroy(ocvf_state *s);
 void     ocvf_metropolis_sweeps(ocvf_state *s, int64_t n);
+void     ocvf_metropolis_domain_sweeps(ocvf_state *s, int64_t n);
 void     ocvf_sw_steps(ocvf_state *s, int64_t n);
 void     ocvf_observables(const ocvf_state *s, ocvf_obs *out);
 void     ocvf_get_sigma(const ocvf_state *s, uint8_t *out);

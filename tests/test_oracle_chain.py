@@ -102,7 +102,7 @@ def batch_z(samples, exact, nbatch=50):
 def run_series(oracle_mod, p, n, algo="met", keys=("n_hb_raw", "n_coop")):
     ch = oracle_mod.Chain(p)
     out = {k: np.empty(n) for k in keys}
-    step = ch.metropolis if algo == "met" else ch.sw
+    step = {"met": ch.metropolis, "sw": ch.sw, "dom": ch.metropolis_domain}[algo]
     for i in range(n):
         step(1)
         o = ch.obs()
