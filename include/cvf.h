@@ -66,7 +66,8 @@ extern "C" {
 /* Reduced units: energies in eps = 5.5 kJ/mol, volumes in v0 = r0^3
  * (Table I).  beta = eps/(k_B T N_A); P is P r0^3 N_A / eps. */
 typedef struct cvf_params {
-    int32_t  L;        /* lattice side, even, 2 <= L <= 32766            */
+    int32_t  L;        /* lattice side, 2 <= L <= 32766; odd L only for
+                          the arm-domain sweep (see below)                */
     int32_t  q;        /* states per bond index, 2..6 (paper: q = 6)     */
     double   beta;     /* inverse reduced temperature, >= 0, finite      */
     double   J;        /* covalent HB energy (Table I: 2.0)              */
@@ -127,15 +128,28 @@ int cvf_init(const cvf_params *p, uint8_t *d_sigma, void *d_work, size_t work_by
  * cells ((x+y) even) then colour 1, arms 0..3 in order inside a cell, each
  * proposing a uniformly chosen different state and accepting it with
  * min(1, exp(-beta dH)) through a 2^32-scaled table.  Asynchronous.
- * nsweeps >= 0. */
+ * nsweeps >= 0; CVF_EINVAL for odd L (the checkerboard needs even L). */
 int cvf_metropolis_sweeps(cvf_state *st, int64_t nsweeps, void *stream);
+
+/* nsweeps MC steps, each a volume move followed by one arm-domain Metropolis
+ * sweep: the paper's own layered partition (Sec. II.C and its figure of the
+ * domains), in 2-D.  Arm a of every cell is a domain whose bond indices
+ * interact only with other domains, so a pass moves all of them at once;
+ * a sweep is four passes, one per arm, in an order drawn per step (a
+ * uniform permutation, Fisher-Yates on Philox(0, t, 0, ORD)).  The move of
+ * arm a of cell (x, y) takes proposal and acceptance words 0, 1 (even x) or
+ * 2, 3 (odd x) of Philox(floor(x/2) + ceil(L/2) y, t, a, DOM), and accepts
+ * through the same table as cvf_metropolis_sweeps.  A different trajectory
+ * from the checkerboard sweep with the same stationary distribution; any L,
+ * odd included.  Asynchronous.  nsweeps >= 0. */
+int cvf_metropolis_domain_sweeps(cvf_state *st, int64_t nsweeps, void *stream);
 
 /* nsteps MC steps, each a volume move followed by one Swendsen-Wang step
  * (Sec. II.D): bond activation, connected-component labelling to the
  * minimum flat index of every cluster (the result Table II converges to),
  * and a cluster-wide shift sigma <- (sigma + r) mod q with r drawn per
- * cluster.  Needs the Swendsen-Wang workspace (CVF_ENOMEM otherwise) and
- * J_sigma >= 0.  Asynchronous. */
+ * cluster.  Needs the Swendsen-Wang workspace (CVF_ENOMEM otherwise),
+ * J_sigma >= 0 and even L (CVF_EINVAL otherwise).  Asynchronous. */
 int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
 
 /* Recount the lattice, evaluate Eq. (1) and (3), and copy everything to
@@ -172,7 +186,8 @@ int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
 #define CVF_K_SW_UNION  3   /* tile-crossing covalent unions       */
 #define CVF_K_SW_FLIP   4   /* cluster shift + recount             */
 #define CVF_K_RECOUNT   5   /* lattice recount (separate launches) */
-#define CVF_K_COUNT     6
+#define CVF_K_MET_DOMAIN 6  /* one arm-domain pass                 */
+#define CVF_K_COUNT     7
 int cvf_timing_enable(cvf_state *st, int enable);
 int cvf_kernel_times(cvf_state *st, int kind, int64_t *launches, double *mean_ms);
 

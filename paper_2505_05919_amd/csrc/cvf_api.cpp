@@ -44,7 +44,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int validate(const cvf_params* p)
 {
     if (!p) return CVF_EINVAL;
-    if (p->L < 2 || p->L > 32766 || (p->L & 1)) return CVF_EINVAL;
+    if (p->L < 2 || p->L > 32766) return CVF_EINVAL;
     if (p->q < 2 || p->q > 6) return CVF_EINVAL;
     if (!(p->beta >= 0.0) || !isfinite(p->beta)) return CVF_EINVAL;
     if (!isfinite(p->J) || !isfinite(p->Jsigma) || !isfinite(p->P) || !isfinite(p->vHB)) return CVF_EINVAL;
@@ -276,7 +276,7 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
 
 int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
 {
-    if (!st || nsweeps < 0) return CVF_EINVAL;
+    if (!st || nsweeps < 0 || (st->p.L & 1)) return CVF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     VolArgs v = st->va;
     v.mode = kVolMet;
@@ -289,9 +289,23 @@ int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
     return CVF_OK;
 }
 
+int cvf_metropolis_domain_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
+{
+    if (!st || nsweeps < 0) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    VolArgs v = st->va;
+    v.mode = kVolMet;
+    v.met_att_add = 4 * (int64_t)st->N;
+    for (int64_t i = 0; i < nsweeps; ++i) {
+        TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        for (uint32_t pass = 0; pass < 4; ++pass) TIMED(CVF_K_MET_DOMAIN, launch_met_domain(st->la, pass, s));
+    }
+    return CVF_OK;
+}
+
 int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
 {
-    if (!st || nsteps < 0) return CVF_EINVAL;
+    if (!st || nsteps < 0 || (st->p.L & 1)) return CVF_EINVAL;
     if (!st->has_sw) return CVF_ENOMEM;
     if (!(st->p.Jsigma >= 0.0)) return CVF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -533,7 +547,7 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
     size_t off_start, off_tstart, off_estart;
     if (desc_bytes < batch_layout(count, &off_start, &off_tstart, &off_estart)) return CVF_ENOMEM;
     for (int32_t c = 0; c < count; ++c)
-        if (!chains[c] || chains[c]->p.q != chains[0]->p.q) return CVF_EINVAL;
+        if (!chains[c] || chains[c]->p.q != chains[0]->p.q || (chains[c]->p.L & 1)) return CVF_EINVAL;
     cvf_batch* b = new (std::nothrow) cvf_batch();
     if (!b) return CVF_EINVAL;
     b->chains.assign(chains, chains + count);

@@ -14,6 +14,8 @@ constexpr uint32_t kStreamVol = 1;    // volume move
 constexpr uint32_t kStreamMet = 2;    // Metropolis proposal + acceptance
 constexpr uint32_t kStreamSwb = 3;    // Swendsen-Wang bond activation
 constexpr uint32_t kStreamSwf = 4;    // Swendsen-Wang cluster shift
+constexpr uint32_t kStreamOrd = 5;    // arm-domain sweep: pass order
+constexpr uint32_t kStreamDom = 6;    // arm-domain sweep: proposal + acceptance
 
 // Per-workgroup partial sums are spread over this many int64 slots so that
 // same-address atomics do not serialise; the volume kernel folds them.
@@ -122,6 +124,8 @@ hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
+// Arm-domain sweep: pass 0..3 of the step's drawn arm order (any L >= 2).
+hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s);
 // step_gate: the recount closes an SW step and is skipped with it.
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
                           hipStream_t s);

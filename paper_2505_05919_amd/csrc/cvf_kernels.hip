@@ -232,6 +232,7 @@ __global__ __launch_bounds__(64) void volume_kernel(VolArgs a)
 }
 
 #include "met_sweep.h"
+#include "met_domain.h"
 
 // Raw buffer helpers for the recount (the sweep kernels have their own).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(uint8_t* p, uint32_t bytes)
@@ -350,10 +351,34 @@ hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int Q>
+void launch_domain_q(const LatticeArgs& a, uint32_t pass, dim3 grid, uint32_t rows, hipStream_t s)
+{
+    if (a.L % 2 == 0) met_domain_kernel<Q, true><<<grid, 256, 0, s>>>(a, pass, rows);
+    else met_domain_kernel<Q, false><<<grid, 256, 0, s>>>(a, pass, rows);
+}
+
+hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s)
+{
+    // column pairs, (L + 1) / 2 per row; rows per wavefront for ~4096 wavefronts
+    const uint32_t groups = ((a.L + 1) / 2 + 63) / 64;
+    const uint32_t wpg = groups >= 4096 ? 1 : 4096 / groups;
+    const uint32_t rows = min(32u, (a.L + wpg - 1) / wpg);
+    const dim3 grid(groups, ((a.L + rows - 1) / rows + 3) / 4);
+    switch (a.q) {
+    case 2: launch_domain_q<2>(a, pass, grid, rows, s); break;
+    case 3: launch_domain_q<3>(a, pass, grid, rows, s); break;
+    case 4: launch_domain_q<4>(a, pass, grid, rows, s); break;
+    case 5: launch_domain_q<5>(a, pass, grid, rows, s); break;
+    default: launch_domain_q<6>(a, pass, grid, rows, s); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
                           hipStream_t s)
 {
-    if (!with_counts) {
+    if (!with_counts && a.L % 2 == 0) {               // column pairs: even L
         // rows per wavefront for ~8192 wavefronts
         const uint32_t groups = (a.L / 2 + 63) / 64;
         const uint32_t wpg = groups >= 8192 ? 1 : 8192 / groups;

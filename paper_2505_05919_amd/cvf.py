@@ -18,9 +18,10 @@ CVF_OK, CVF_EINVAL, CVF_ENOMEM, CVF_EHIP, CVF_ESTATE = 0, -1, -2, -3, -4
 CVF_ALGO_METROPOLIS, CVF_ALGO_SW = 1, 2
 CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
 (CVF_K_VOLUME, CVF_K_MET_SWEEP, CVF_K_SW_BONDS, CVF_K_SW_UNION, CVF_K_SW_FLIP,
- CVF_K_RECOUNT, CVF_K_COUNT) = range(7)
+ CVF_K_RECOUNT, CVF_K_MET_DOMAIN, CVF_K_COUNT) = range(8)
 
 EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
+           "cvf_metropolis_domain_sweeps",
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
            "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_set_stop", "cvf_batch_desc_bytes", "cvf_batch_create",
            "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
@@ -72,6 +73,7 @@ def lib():
         L.cvf_workspace_bytes.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.cvf_init.argtypes = [P, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.cvf_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf_metropolis_domain_sweeps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_observables.argtypes = [vp, ctypes.POINTER(cvf_obs), vp]
         L.cvf_labels.argtypes = [vp, vp, vp]
@@ -152,6 +154,10 @@ def cvf_init(p: cvf_params, sigma, work, stream=None) -> ctypes.c_void_p:
 
 def cvf_metropolis_sweeps(st, nsweeps: int, stream=None):
     _check("cvf_metropolis_sweeps", lib().cvf_metropolis_sweeps(st, nsweeps, _stream(stream)))
+
+
+def cvf_metropolis_domain_sweeps(st, nsweeps: int, stream=None):
+    _check("cvf_metropolis_domain_sweeps", lib().cvf_metropolis_domain_sweeps(st, nsweeps, _stream(stream)))
 
 
 def cvf_sw_steps(st, nsteps: int, stream=None):
@@ -286,6 +292,10 @@ class Chain:
 
     def metropolis(self, n):
         cvf_metropolis_sweeps(self.h, n, self.stream)
+        return self
+
+    def metropolis_domain(self, n):
+        cvf_metropolis_domain_sweeps(self.h, n, self.stream)
         return self
 
     def sw(self, n):

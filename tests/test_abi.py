@@ -55,7 +55,7 @@ def test_workspace_bytes(cvf):
     assert both - met < 25 * N + 96 * tiles + 1024
 
 
-@pytest.mark.parametrize("field,value", [("L", 3), ("L", 0), ("L", 32768), ("q", 1), ("q", 7),
+@pytest.mark.parametrize("field,value", [("L", 1), ("L", 0), ("L", 32768), ("q", 1), ("q", 7),
                                          ("beta", -1.0), ("beta", float("inf")), ("v_init", 0.5),
                                          ("dv_max", -0.1), ("flags", 8), ("reserved", 1)])
 def test_invalid_params_rejected(cvf, field, value):
@@ -68,6 +68,13 @@ def test_invalid_params_rejected(cvf, field, value):
     rc = cvf.lib().cvf_init(ctypes.byref(p), ctypes.c_void_p(4096), ctypes.c_void_p(4096), 1 << 20, None,
                             ctypes.byref(h))
     assert rc == cvf.CVF_EINVAL
+
+
+def test_odd_L_is_a_valid_parameter(cvf):
+    # odd L runs the arm-domain sweep only; the checkerboard sweep, SW steps
+    # and batches reject it when called
+    p = cvf.cvf_params_from_si(300.0, 0.1, L=1413)
+    assert cvf.cvf_workspace_bytes(p, cvf.CVF_ALGO_METROPOLIS) < 8192
 
 
 def test_init_rejects_small_or_misaligned_workspace(cvf):

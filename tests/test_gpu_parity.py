@@ -51,7 +51,7 @@ def check_obs(og, oo, ctx):
 
 
 def run_pair(cvf, oracle_mod, op, plan, labels=False, algo_mask=3):
-    """plan: list of ("met"|"sw", n) applied to both; compares after each item."""
+    """plan: list of ("met"|"dom"|"sw", n) applied to both; compares after each item."""
     ctx = f"L={op.L} q={op.q} seed={op.seed} beta={op.beta:.6g} P={op.P:.6g} flags={op.flags} plan={plan}"
     say("case " + ctx)
     ch = cvf.Chain(gpu_params(cvf, op), algo_mask)
@@ -61,6 +61,9 @@ def run_pair(cvf, oracle_mod, op, plan, labels=False, algo_mask=3):
         if algo == "met":
             ch.metropolis(n)
             oc.metropolis(n)
+        elif algo == "dom":
+            ch.metropolis_domain(n)
+            oc.metropolis_domain(n)
         else:
             ch.sw(n)
             oc.sw(n)
