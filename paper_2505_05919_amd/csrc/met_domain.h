@@ -39,13 +39,63 @@ __device__ __forceinline__ uint32_t domain_arm(const LatticeArgs& a, uint32_t t,
     return (ord >> (4 * pass)) & 15u;
 }
 
-__device__ __forceinline__ uint32_t pick_arm(const uint32_t (&s)[4], uint32_t arm)
-{
-    return arm == 0 ? s[0] : arm == 1 ? s[1] : arm == 2 ? s[2] : s[3];
-}
-
+// The rows of one wavefront for pass arm ARM (a template, so that the facing
+// plane, the facing cell and the three other arms are fixed at compile time).
 // EVEN: L even, so a pair never leaves its row and its two bytes of a plane
 // are one aligned 16-bit word.
+template <int Q, bool EVEN, int ARM>
+__device__ __forceinline__ uint32_t dom_rows(const LatticeArgs& a, const uint2* tbl, uint32_t t, uint32_t pr,
+                                             uint32_t y0, uint32_t y1)
+{
+    constexpr int B1 = ARM == 0 ? 1 : 0, B2 = ARM <= 1 ? 2 : 1, B3 = ARM == 3 ? 2 : 3;   // the other arms
+    const uint32_t L = a.L, N = a.N, np = (L + 1) >> 1;
+    const uint32_t x0 = 2 * pr, x1 = x0 + 1;
+    const bool has1 = x1 < L;
+    const uint32_t c1 = has1 ? x1 : x0;                    // a lone cell reads its own column twice
+    // column of the facing cell: the x neighbours for arms 0, 1, else the same
+    uint32_t fx0 = x0, fx1 = c1;
+    if (ARM == 0) {
+        fx0 = (x0 + 1 == L) ? 0 : x0 + 1;
+        fx1 = (c1 + 1 == L) ? 0 : c1 + 1;
+    } else if (ARM == 1) {
+        fx0 = (x0 == 0) ? L - 1 : x0 - 1;
+        fx1 = (c1 == 0) ? L - 1 : c1 - 1;
+    }
+    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * N);
+    const uint32_t fp = (ARM ^ 1) * N, ap = ARM * N;
+    uint32_t wsum = 0;
+    for (uint32_t y = y0; y < y1; ++y) {
+        const uint32_t o = y * L;
+        const uint32_t fy = (ARM == 2) ? ((y + 1 == L) ? 0 : y + 1) : (ARM == 3) ? ((y == 0) ? L - 1 : y - 1) : y;
+        uint32_t s0[4], s1[4];
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) {
+            if (EVEN) {
+                const uint32_t d = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)x0, (int)(b * N + o), 0);
+                s0[b] = (d & 255u) << 2;
+                s1[b] = (d >> 8) << 2;
+            } else {
+                s0[b] = ld8(rs, x0, b * N + o) << 2;
+                s1[b] = ld8(rs, c1, b * N + o) << 2;
+            }
+        }
+        const uint32_t f0 = ld8(rs, fx0, fp + fy * L) << 2, f1 = ld8(rs, fx1, fp + fy * L) << 2;
+        const uint4 w = philox(pr + np * y, t, ARM, kStreamDom, a.key0, a.key1);
+        uint32_t a0 = s0[ARM], a1 = s1[ARM];
+        met_arm<Q>(a0, (1u << s0[B1]) + (1u << s0[B2]) + (1u << s0[B3]) + (8u << f0), w.x, w.y, tbl, wsum);
+        const uint32_t wkeep = wsum;                       // a lone cell's stand-in moves nothing
+        met_arm<Q>(a1, (1u << s1[B1]) + (1u << s1[B2]) + (1u << s1[B3]) + (8u << f1), w.z, w.w, tbl, wsum);
+        if (EVEN) {
+            st16(rs, (a0 >> 2) | ((a1 >> 2) << 8), x0, ap + o);
+        } else {
+            if (!has1) wsum = wkeep;
+            st8(rs, a0 >> 2, x0, ap + o);
+            if (has1) st8(rs, a1 >> 2, x1, ap + o);
+        }
+    }
+    return wsum;
+}
+
 template <int Q, bool EVEN>
 __global__ __launch_bounds__(256) void met_domain_kernel(LatticeArgs a, uint32_t pass, uint32_t rows)
 {
@@ -54,61 +104,20 @@ __global__ __launch_bounds__(256) void met_domain_kernel(LatticeArgs a, uint32_t
     if (skip) return;                                      // step limit reached
     __shared__ uint2 tbl[32];
     const uint32_t arm = __builtin_amdgcn_readfirstlane(domain_arm(a, t, pass));
-    const uint32_t L = a.L, N = a.N, np = (L + 1) >> 1;
+    const uint32_t L = a.L, np = (L + 1) >> 1;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t pr = blockIdx.x * 64 + lane;
     const uint32_t y0 = (blockIdx.y * 4 + wave) * rows;
-    const bool active = pr < np && y0 < L;
-    const uint32_t x0 = 2 * pr, x1 = x0 + 1;
-    const bool has1 = x1 < L;
-    const uint32_t c1 = has1 ? x1 : x0;                    // a lone cell reads its own column twice
-    // column of the facing cell (arms 0, 1: the x neighbours; arms 2, 3: the
-    // same column, another row)
-    uint32_t fx0 = x0, fx1 = c1;
-    if (arm == 0) {
-        fx0 = (x0 + 1 == L) ? 0 : x0 + 1;
-        fx1 = (c1 + 1 == L) ? 0 : c1 + 1;
-    } else if (arm == 1) {
-        fx0 = (x0 == 0) ? L - 1 : x0 - 1;
-        fx1 = (c1 == 0) ? L - 1 : c1 - 1;
-    }
-    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * N);
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
-    if (active) {
+    if (pr < np && y0 < L) {
         const uint32_t y1 = min(y0 + rows, L);
-        const uint32_t fp = (arm ^ 1u) * N, ap = arm * N;
-        for (uint32_t y = y0; y < y1; ++y) {
-            const uint32_t o = y * L;
-            const uint32_t fy = (arm == 2) ? ((y + 1 == L) ? 0 : y + 1) : (arm == 3) ? ((y == 0) ? L - 1 : y - 1) : y;
-            uint32_t s0[4], s1[4];
-#pragma unroll
-            for (uint32_t b = 0; b < 4; ++b) {
-                if (EVEN) {
-                    const uint32_t d = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)x0, (int)(b * N + o), 0);
-                    s0[b] = (d & 255u) << 2;
-                    s1[b] = (d >> 8) << 2;
-                } else {
-                    s0[b] = ld8(rs, x0, b * N + o) << 2;
-                    s1[b] = ld8(rs, c1, b * N + o) << 2;
-                }
-            }
-            const uint32_t f0 = ld8(rs, fx0, fp + fy * L) << 2, f1 = ld8(rs, fx1, fp + fy * L) << 2;
-            const uint4 w = philox(pr + np * y, t, arm, kStreamDom, a.key0, a.key1);
-            uint32_t a0 = pick_arm(s0, arm), a1 = pick_arm(s1, arm);
-            const uint32_t all0 = (1u << s0[0]) + (1u << s0[1]) + (1u << s0[2]) + (1u << s0[3]);
-            const uint32_t all1 = (1u << s1[0]) + (1u << s1[1]) + (1u << s1[2]) + (1u << s1[3]);
-            met_arm<Q>(a0, all0 - (1u << a0) + (8u << f0), w.x, w.y, tbl, wsum);
-            const uint32_t wkeep = wsum;                   // a lone cell's stand-in moves nothing
-            met_arm<Q>(a1, all1 - (1u << a1) + (8u << f1), w.z, w.w, tbl, wsum);
-            if (EVEN) {
-                st16(rs, (a0 >> 2) | ((a1 >> 2) << 8), x0, ap + o);
-            } else {
-                if (!has1) wsum = wkeep;
-                st8(rs, a0 >> 2, x0, ap + o);
-                if (has1) st8(rs, a1 >> 2, x1, ap + o);
-            }
+        switch (arm) {                                     // wave-uniform
+        case 0: wsum = dom_rows<Q, EVEN, 0>(a, tbl, t, pr, y0, y1); break;
+        case 1: wsum = dom_rows<Q, EVEN, 1>(a, tbl, t, pr, y0, y1); break;
+        case 2: wsum = dom_rows<Q, EVEN, 2>(a, tbl, t, pr, y0, y1); break;
+        default: wsum = dom_rows<Q, EVEN, 3>(a, tbl, t, pr, y0, y1); break;
         }
     }
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
