@@ -227,6 +227,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--skip-sw", action="store_true")
+    ap.add_argument("--skip-domain", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--serve-jobs", type=int, default=120,
@@ -322,6 +323,38 @@ def main():
             ch.close()
         del sch
 
+    # ---------------- arm-domain Metropolis L = 4096 ----------------
+    dom = None
+    if not args.skip_domain:
+        log(f"arm-domain: {len(met_jobs)} chains L={met_jobs[0].L}, warmup {W}, steps {K}")
+        dch = [make_chain(cvf, j.L, j.T, j.P, j.seed, cvf.CVF_ALGO_METROPOLIS) for j in met_jobs]
+
+        def dom_step(i):
+            dch[i % len(dch)].metropolis_domain(1)
+
+        for i in range(W * len(dch)):
+            dom_step(i)
+        t_dom = timed(torch, dom_step, K)
+        kt = instrumented(cvf, dch, dom_step, K, [cvf.CVF_K_MET_DOMAIN])
+        n_pass, pass_ms = kt[cvf.CVF_K_MET_DOMAIN]
+        # one pass moves one arm of every cell: N updates, 6 algorithmic bytes
+        # each (the cell's four bond indices and the facing one read, one written)
+        pass_s = pass_ms * 1e-3
+        dom_tops = N * ALU_OPS_PER_UPDATE / pass_s / 1e12
+        dom_gbs = N * 6 / pass_s / 1e9
+        dom = {"L": met_jobs[0].L, "updates_per_ns": round(4 * N * K / t_dom / 1e9, 2),
+               "ms_per_sweep": round(t_dom / K * 1e3, 4), "passes_timed": n_pass,
+               "pass_mean_us": round(pass_ms * 1e3, 2),
+               "alu": {"achieved": round(dom_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                       "frac": round(dom_tops / VALU_PEAK_TOPS, 4)},
+               "hbm": {"achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": 6}}
+        log(f"arm-domain: {dom}")
+        for ch in dch:
+            assert ch.obs()["consistent"] == 1
+            ch.close()
+        del dch
+
     batched = None
     if not args.skip_batch:
         batched = bench_batched(torch, cvf, args.batch_sweeps, args.alone_sweeps)
@@ -358,6 +391,7 @@ def main():
                                "sweep + one volume move of one chain (round robin); SW L=1414 likewise",
                    "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
         "sw": sw,
+        "met_domain": dom,
         "batched": batched,
         "served": served,
         "roofline": roofline,
