@@ -96,6 +96,45 @@ def instrumented(cvf, chains, fn, K, kinds):
     return out
 
 
+def bench_autocorr(torch, cvf, L=256, points=((270.0, 7), (300.0, 9)), n_time=2000, max_lag=2000):
+    """Sec. III.A / III.C at the C2 SW lattice size: after a warm-up, M(t)
+    recorded on the device after every step, C_M and tau (the 1/e lag) for
+    checkerboard Metropolis and SW, each step timed separately (no
+    recording), and the cost of one independent configuration = tau x time
+    per step.  A tau beyond max_lag is reported as null."""
+    import math
+    from paper_2505_05919_amd import autocorr
+    warm = {"met": 20000, "sw": 2000}
+    n_rec = {"met": 50000, "sw": 5000}
+    out = {"L": L, "P_MPa": 0.1, "max_lag": max_lag, "points": []}
+    for T, seed in points:
+        pt = {"T_K": T}
+        for algo in ("met", "sw"):
+            ch = make_chain(cvf, L, T, 0.1, seed, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+            step = ch.metropolis if algo == "met" else ch.sw
+            step(warm[algo])
+            counts = autocorr.record_counts(cvf, ch, step, n_rec[algo])
+            M = autocorr.order_parameter(counts, 4 * L * L)
+            C = autocorr.c_m(M, min(max_lag, n_rec[algo] // 2))
+            tau = autocorr.tau_1e(C)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(n_time)
+            torch.cuda.synchronize()
+            t_step = (time.perf_counter() - t0) / n_time
+            assert ch.obs()["consistent"] == 1
+            ch.close()
+            ok = not math.isnan(tau)
+            pt[algo] = {"warmup_steps": warm[algo], "steps_recorded": n_rec[algo],
+                        "tau_steps": round(float(tau), 3) if ok else None, "C_M_1": round(float(C[1]), 4),
+                        "step_us": round(t_step * 1e6, 2),
+                        "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None}
+        cm, cs = pt["met"]["cost_per_independent_us"], pt["sw"]["cost_per_independent_us"]
+        pt["cheaper"] = None if cs is None else ("sw" if cm is None or cs < cm else "met")
+        out["points"].append(pt)
+    return out
+
+
 def cpu_baseline(budget_s: float):
     """The oracle as it stands (single thread), Metropolis on the headline
     lattice, sweeps until the budget is used."""
@@ -228,6 +267,7 @@ def main():
                     help="also run a plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--skip-sw", action="store_true")
     ap.add_argument("--skip-domain", action="store_true")
+    ap.add_argument("--skip-autocorr", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--serve-jobs", type=int, default=120,
@@ -355,6 +395,12 @@ def main():
             ch.close()
         del dch
 
+    # ---------------- autocorrelation and cost per independent configuration ----------------
+    auto = None
+    if not args.skip_autocorr:
+        auto = bench_autocorr(torch, cvf)
+        log(f"autocorr: {auto}")
+
     batched = None
     if not args.skip_batch:
         batched = bench_batched(torch, cvf, args.batch_sweeps, args.alone_sweeps)
@@ -392,6 +438,7 @@ def main():
                    "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
         "sw": sw,
         "met_domain": dom,
+        "autocorr": auto,
         "batched": batched,
         "served": served,
         "roofline": roofline,

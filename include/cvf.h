@@ -113,7 +113,8 @@ int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
  * cell) and 96 bytes per 64 x 32-cell tile.  Host only. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
-/* Create a chain.  d_sigma: 4*L*L bytes of device memory, layout above;
+/* Create a chain.  d_sigma: 4*L*L bytes of device memory (4-byte aligned:
+ * the sweeps move dwords), layout above;
  * filled from Philox stream INIT (sigma[a][c] = floor(w_a q / 2^32) of the
  * block at counter (c, 0, 0, INIT)) unless CVF_KEEP_SIGMA.  d_work /
  * work_bytes: caller-owned device workspace (256-byte aligned), at least
@@ -155,6 +156,15 @@ int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
 /* Recount the lattice, evaluate Eq. (1) and (3), and copy everything to
  * *out.  Synchronises stream. */
 int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
+
+/* Add the state counts N_q' of the current configuration (the number of
+ * bond indices in state q', q' = 0..5, from which Sec. III.A builds the
+ * order parameter M = max N_q' over the number of bond indices, 4N in 2-D,
+ * and its autocorrelation C_M) to the six int64 at d_counts (device
+ * memory, 8-byte aligned, zeroed by the caller beforehand: the kernel
+ * accumulates).  No host synchronisation, so a caller can record one row
+ * per step of a long run and read the series once.  Asynchronous. */
+int cvf_state_counts(cvf_state *st, int64_t *d_counts, void *stream);
 
 /* Write the cluster labels of the last Swendsen-Wang step (4*L*L uint32,
  * label[idx] = smallest flat index in idx's cluster) to device memory

@@ -196,7 +196,7 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     if (!out || !d_sigma || !d_work) return CVF_EINVAL;
     int rc = validate(p);
     if (rc) return rc;
-    if (((uintptr_t)d_work & 255) != 0) return CVF_EINVAL;
+    if (((uintptr_t)d_work & 255) != 0 || ((uintptr_t)d_sigma & 3) != 0) return CVF_EINVAL;
     if (work_bytes < kBaseBytes) return CVF_ENOMEM;
     cvf_state* st = new (std::nothrow) cvf_state();
     if (!st) return CVF_EINVAL;
@@ -338,6 +338,12 @@ int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
     if (e != hipSuccess) return CVF_EHIP;
     *out = tmp;
     return CVF_OK;
+}
+
+int cvf_state_counts(cvf_state* st, int64_t* d_counts, void* stream)
+{
+    if (!st || !d_counts || ((uintptr_t)d_counts & 7) != 0) return CVF_EINVAL;
+    return hip_status(launch_state_counts(st->la, d_counts, (hipStream_t)stream));
 }
 
 int cvf_labels(cvf_state* st, uint32_t* d_out, void* stream)

@@ -130,6 +130,8 @@ hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s)
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
                           hipStream_t s);
 hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
+// N_q' of the current sigma added to out[0..5] (sigma 4-byte aligned).
+hipError_t launch_state_counts(const LatticeArgs& a, int64_t* out, hipStream_t s);
 hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
                             double Jsigma, double P, double vHB, hipStream_t s);
 // Tiled SW step: bonds + in-tile unions, the tile-crossing links, then the

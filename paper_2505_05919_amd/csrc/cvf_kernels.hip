@@ -247,6 +247,26 @@ __device__ __forceinline__ uint32_t ld8b(__amdgpu_buffer_rsrc_t r, uint32_t voff
 
 #include "sw_step.h"
 
+// N_q' of the current sigma (q' < 6), added to out[0..5].  The planes are
+// read as 32-bit words; the bytes of w equal to k are the zero bytes of
+// x = w ^ k 0x01010101, flagged in bit 7 of every byte of
+// ~(((x & 0x7F7F7F7F) + 0x7F7F7F7F) | x | 0x7F7F7F7F) (no carry crosses a
+// byte), and counted with one popcount.
+__global__ __launch_bounds__(kBlock) void state_counts_kernel(const uint32_t* __restrict__ words, uint32_t nwords,
+                                                              int64_t* out)
+{
+    int c[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nwords; i += gridDim.x * kBlock) {
+        const uint32_t w = words[i];
+#pragma unroll
+        for (uint32_t k = 0; k < 6; ++k) {
+            const uint32_t x = w ^ (k * 0x01010101u);
+            c[k] += __popc(~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu));
+        }
+    }
+    block_add<6>(c, out, 1);
+}
+
 __global__ void obs_zero_kernel(DevObs* o)
 {
     if (threadIdx.x < 8) o->acc[threadIdx.x] = 0;
@@ -390,6 +410,13 @@ hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int wi
         return hipGetLastError();
     }
     recount_kernel<<<grid_for(a.N), kBlock, 0, s>>>(a, out, spread, with_counts, step_gate);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_counts(const LatticeArgs& a, int64_t* out, hipStream_t s)
+{
+    const uint32_t nwords = a.N;                          // 4N bytes
+    state_counts_kernel<<<grid_for(nwords), kBlock, 0, s>>>(reinterpret_cast<const uint32_t*>(a.sigma), nwords, out);
     return hipGetLastError();
 }
 

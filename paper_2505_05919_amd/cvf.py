@@ -21,7 +21,7 @@ CVF_NO_VOLUME_MOVE, CVF_KEEP_SIGMA = 1, 2
  CVF_K_RECOUNT, CVF_K_MET_DOMAIN, CVF_K_COUNT) = range(8)
 
 EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropolis_sweeps",
-           "cvf_metropolis_domain_sweeps",
+           "cvf_metropolis_domain_sweeps", "cvf_state_counts",
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
            "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_set_stop", "cvf_batch_desc_bytes", "cvf_batch_create",
            "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
@@ -74,6 +74,7 @@ def lib():
         L.cvf_init.argtypes = [P, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.cvf_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_metropolis_domain_sweeps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf_state_counts.argtypes = [vp, vp, vp]
         L.cvf_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_observables.argtypes = [vp, ctypes.POINTER(cvf_obs), vp]
         L.cvf_labels.argtypes = [vp, vp, vp]
@@ -158,6 +159,12 @@ def cvf_metropolis_sweeps(st, nsweeps: int, stream=None):
 
 def cvf_metropolis_domain_sweeps(st, nsweeps: int, stream=None):
     _check("cvf_metropolis_domain_sweeps", lib().cvf_metropolis_domain_sweeps(st, nsweeps, _stream(stream)))
+
+
+def cvf_state_counts(st, d_counts, stream=None):
+    """Add the six state counts N_q' of the current sigma to the int64[6]
+    at device address d_counts (an int, e.g. a tensor's data_ptr())."""
+    _check("cvf_state_counts", lib().cvf_state_counts(st, ctypes.c_void_p(d_counts), _stream(stream)))
 
 
 def cvf_sw_steps(st, nsteps: int, stream=None):

@@ -87,6 +87,9 @@ def test_init_rejects_small_or_misaligned_workspace(cvf):
                       ctypes.byref(h)) == cvf.CVF_ENOMEM
     assert L.cvf_init(ctypes.byref(p), None, ctypes.c_void_p(4096), 1 << 20, None,
                       ctypes.byref(h)) == cvf.CVF_EINVAL
+    # sigma must be 4-byte aligned (the sweeps move dwords)
+    assert L.cvf_init(ctypes.byref(p), ctypes.c_void_p(4096 + 2), ctypes.c_void_p(4096), 1 << 20, None,
+                      ctypes.byref(h)) == cvf.CVF_EINVAL
 
 
 def test_null_state_and_strerror(cvf):
@@ -94,6 +97,8 @@ def test_null_state_and_strerror(cvf):
     assert L.cvf_metropolis_sweeps(None, 1, None) == cvf.CVF_EINVAL
     assert L.cvf_sw_steps(None, 1, None) == cvf.CVF_EINVAL
     assert L.cvf_destroy(None) == cvf.CVF_EINVAL
+    assert L.cvf_metropolis_domain_sweeps(None, 1, None) == cvf.CVF_EINVAL
+    assert L.cvf_state_counts(None, ctypes.c_void_p(4096), None) == cvf.CVF_EINVAL
     assert L.cvf_params_from_si(0.0, 0.1, None) == cvf.CVF_EINVAL
     for code in (0, -1, -2, -3, -4, -99):
         assert isinstance(cvf.cvf_strerror(code), str)
