@@ -96,39 +96,22 @@ def instrumented(cvf, chains, fn, K, kinds):
     return out
 
 
-def bench_autocorr(torch, cvf, L=256, points=((270.0, 7), (300.0, 9)), n_time=2000, max_lag=2000):
-    """Sec. III.A / III.C at the C2 SW lattice size: after a warm-up, M(t)
-    recorded on the device after every step, C_M and tau (the 1/e lag) for
-    checkerboard Metropolis and SW, each step timed separately (no
-    recording), and the cost of one independent configuration = tau x time
-    per step.  A tau beyond max_lag is reported as null."""
-    import math
+def bench_autocorr(torch, cvf, L=256, points=((270.0, 7), (300.0, 9))):
+    """Sec. III.A / III.C at the C2 SW lattice size: tau of the order
+    parameter and the cost of one independent configuration for checkerboard
+    Metropolis and SW (autocorr.measure: warm-up, M(t) recorded on the device
+    after every step, C_M, tau = the 1/e lag, steps timed without
+    recording)."""
     from paper_2505_05919_amd import autocorr
     warm = {"met": 20000, "sw": 2000}
     n_rec = {"met": 50000, "sw": 5000}
-    out = {"L": L, "P_MPa": 0.1, "max_lag": max_lag, "points": []}
+    out = {"L": L, "P_MPa": 0.1, "max_lag": 2000, "points": []}
     for T, seed in points:
         pt = {"T_K": T}
         for algo in ("met", "sw"):
-            ch = make_chain(cvf, L, T, 0.1, seed, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
-            step = ch.metropolis if algo == "met" else ch.sw
-            step(warm[algo])
-            counts = autocorr.record_counts(cvf, ch, step, n_rec[algo])
-            M = autocorr.order_parameter(counts, 4 * L * L)
-            C = autocorr.c_m(M, min(max_lag, n_rec[algo] // 2))
-            tau = autocorr.tau_1e(C)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            step(n_time)
-            torch.cuda.synchronize()
-            t_step = (time.perf_counter() - t0) / n_time
-            assert ch.obs()["consistent"] == 1
-            ch.close()
-            ok = not math.isnan(tau)
-            pt[algo] = {"warmup_steps": warm[algo], "steps_recorded": n_rec[algo],
-                        "tau_steps": round(float(tau), 3) if ok else None, "C_M_1": round(float(C[1]), 4),
-                        "step_us": round(t_step * 1e6, 2),
-                        "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None}
+            r = autocorr.measure(cvf, torch, L, T, 0.1, seed, algo, warm[algo], n_rec[algo])
+            assert r.pop("consistent")
+            pt[algo] = r
         cm, cs = pt["met"]["cost_per_independent_us"], pt["sw"]["cost_per_independent_us"]
         pt["cheaper"] = None if cs is None else ("sw" if cm is None or cs < cm else "met")
         out["points"].append(pt)

@@ -13,6 +13,7 @@ The counts come from cvf_state_counts, one row per step, accumulated on the
 device and read once; the statistics are host arithmetic on that series.
 """
 import math
+import time
 
 import numpy as np
 
@@ -61,3 +62,31 @@ def record_counts(cvf, chain, step, nsteps: int):
         step(1)
         cvf.cvf_state_counts(chain.h, base + 48 * i, chain.stream)
     return out.cpu().numpy()
+
+
+def measure(cvf, torch, L: int, T: float, P: float, seed: int, algo: str, warm: int, n_rec: int,
+            n_time: int = 2000, max_lag: int = 2000) -> dict:
+    """tau, time per step and cost of one independent configuration (Sec.
+    III.C) of one algorithm ("met" or "sw") at one state point: a warm-up,
+    n_rec recorded steps, C_M up to min(max_lag, n_rec / 2), then n_time
+    steps timed without recording.  tau and the cost are None when C_M does
+    not reach 1/e inside the window."""
+    p = cvf.cvf_params_from_si(T, P, L=L, seed=seed)
+    ch = cvf.Chain(p, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+    step = ch.metropolis if algo == "met" else ch.sw
+    step(warm)
+    counts = record_counts(cvf, ch, step, n_rec)
+    C = c_m(order_parameter(counts, 4 * L * L), min(max_lag, n_rec // 2))
+    tau = tau_1e(C)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(n_time)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / n_time
+    consistent = ch.obs()["consistent"] == 1
+    ch.close()
+    ok = not math.isnan(tau)
+    return {"warmup_steps": warm, "steps_recorded": n_rec, "tau_steps": round(float(tau), 3) if ok else None,
+            "C_M_1": round(float(C[1]), 4), "step_us": round(t_step * 1e6, 2),
+            "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None,
+            "consistent": consistent}

@@ -11,7 +11,9 @@ quanta and queued jobs take their place, so requests that arrive while others
 run are admitted as memory and slots free up.
 
 Every job's result is a pure function of its parameters and seed: identical
-alone and in the mix (tested).  All device work goes through libcvf.
+alone and in the mix (tested).  An optional policy (policy.AlgoPolicy)
+chooses each job's algorithm when it arrives.  All device work goes through
+libcvf.
 """
 from __future__ import annotations
 
@@ -21,6 +23,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cvf
+from .policy import AlgoPolicy
 from .workloads import Job
 
 
@@ -65,6 +68,7 @@ class Server:
     quantum: int = 50                   # MC steps per quantum for every resident job
     graph_block: int = 0                # >0: batched sweeps replay a hipGraph of this many
     keep_digest: bool = False
+    policy: AlgoPolicy | None = None    # algorithm choice at arrival (None: as submitted)
     records: list = field(default_factory=list)
     peak_resident_bytes: int = 0
     peak_resident_jobs: int = 0
@@ -98,7 +102,8 @@ class Server:
             tnow = now()
             tp = time.perf_counter()
             while pending and (not realtime or pending[0].arrival <= tnow):
-                queue.append(pending.pop(0))
+                job = pending.pop(0)
+                queue.append(self.policy.apply(job) if self.policy else job)
             # admission: FIFO, by footprint and slots
             while queue and len(running) < self.max_slots:
                 fp = footprint(queue[0])

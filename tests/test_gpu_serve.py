@@ -55,3 +55,28 @@ def test_fcfs_latency_model(serve):
     jobs = [Job(8, 300.0, 0.1, 1, "met", 1, a) for a in (0.0, 0.5, 0.6, 3.0)]
     lat = serve.fcfs_latencies(jobs, [1.0, 1.0, 1.0, 1.0])
     assert np.allclose(lat, [1.0, 1.5, 2.4, 1.0])
+
+
+def test_served_with_algorithm_policies(serve):
+    """Jobs on both sides of the paper's 208 K switch: the threshold policy
+    picks each job's algorithm at arrival, and every served job equals the
+    same job run alone with that algorithm.  A short calibration feeds the
+    cost policy."""
+    import dataclasses
+
+    import torch
+    from paper_2505_05919_amd import cvf
+    from paper_2505_05919_amd.policy import AlgoPolicy, calibrate
+    jobs = [dataclasses.replace(j, T=200.0 if k % 2 else 215.0) for k, j in enumerate(small_stream(14))]
+    srv = serve.Server(memory_budget=1 << 34, max_slots=16, quantum=5, keep_digest=True,
+                       policy=AlgoPolicy("threshold"))
+    recs = srv.run(jobs, realtime=False)
+    assert len(recs) == len(jobs)
+    for r in recs:
+        assert r.job.algo == ("sw" if r.job.T < 208.0 else "met")
+        o, dg, _ = serve.run_alone(r.job)
+        assert r.digest == dg and r.obs == o, r.job
+    table = calibrate(cvf, torch, [205.0, 300.0], L=32, warm={"met": 200, "sw": 50}, n_rec={"met": 2000, "sw": 400})
+    assert set(table) == {205.0, 300.0}
+    pol = AlgoPolicy("cost", table=table)
+    assert {pol.choose(j) for j in jobs} <= {"met", "sw"}
