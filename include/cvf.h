@@ -11,8 +11,9 @@
  *   state      {v_iso, sigma}            Sec. II.B (configuration)
  *   enthalpy   H = U_LJ - J N_HB - J_sigma N_sigma + P V,
  *              V = V_iso + v_HB N_HB     Eq. (1), Eq. (3), Table I
- *   MC step    volume move, then the sigma update (Metropolis sweep or
- *              Swendsen-Wang step)       Sec. II.B-II.D
+ *   MC step    volume move, then the sigma update: a checkerboard or an
+ *              arm-domain Metropolis sweep, or a Swendsen-Wang step
+ *                                        Sec. II.B-II.D
  *
  * Layout (part of the ABI).  sigma is caller-owned device memory of 4*L*L
  * bytes, plane-major as in Sec. II.C: sigma[a*N + c], N = L*L, cell
@@ -33,8 +34,9 @@
  *    allocates no device memory.  Host state is owned by the library and
  *    freed by cvf_destroy.
  *  - stream: a hipStream_t passed as void* (NULL = the null stream).  All
- *    calls are asynchronous on that stream except cvf_observables and
- *    cvf_kernel_times, which synchronise it.
+ *    calls are asynchronous on that stream except cvf_observables,
+ *    cvf_labels, cvf_kernel_times, cvf_batch_create, cvf_batch_set_rows and
+ *    cvf_batch_autotune, which synchronise it.
  *  - Threading: a cvf_state is not thread-safe; distinct states are
  *    independent and may run concurrently on different streams.
  */
@@ -216,16 +218,19 @@ typedef struct cvf_batch cvf_batch;
 /* Device bytes for the descriptor table of `count` chains. */
 int cvf_batch_desc_bytes(int32_t count, size_t *bytes);
 
-/* Group `count` existing chains (created by cvf_init, all with the same q;
- * each keeps its own sigma and workspace).  d_desc: caller-owned device
- * memory of cvf_batch_desc_bytes(count) bytes, 256-byte aligned.  The
- * chains must outlive the batch; the batch holds no device memory of its own
- * besides a private capture stream for graphs.  Asynchronous on stream. */
+/* Group `count` existing chains (created by cvf_init, all with the same q
+ * and even L -- CVF_EINVAL otherwise; each keeps its own sigma and
+ * workspace).  d_desc: caller-owned device memory of
+ * cvf_batch_desc_bytes(count) bytes, 256-byte aligned.  The chains must
+ * outlive the batch; the batch holds no device memory of its own besides a
+ * private capture stream for graphs.  Uploads the descriptor table on stream
+ * and waits for the copy. */
 int cvf_batch_create(cvf_state *const *chains, int32_t count, void *d_desc, size_t desc_bytes,
                      void *stream, cvf_batch **out);
 
 /* Launch shape: every wavefront walks `rows` rows (even, 2..32); 0 restores
- * each chain's own default.  Invalidates captured graphs.  Asynchronous. */
+ * each chain's own default.  Invalidates captured graphs.  Re-uploads the
+ * descriptor table on stream and waits for the copy. */
 int cvf_batch_set_rows(cvf_batch *b, int32_t rows, void *stream);
 
 /* nsweeps Metropolis MC steps of every chain.  graph_block > 0: the sweeps
@@ -245,6 +250,8 @@ int cvf_batch_sw_steps(cvf_batch *b, int64_t nsteps, void *stream);
  * Synchronises stream. */
 int cvf_batch_autotune(cvf_batch *b, int32_t sweeps, void *stream, int32_t *rows_out);
 
+/* Release the batch's host state, its captured graph and capture stream;
+ * the chains and d_desc stay with the caller. */
 int cvf_batch_destroy(cvf_batch *b);
 
 /* Static description of an error code. */
