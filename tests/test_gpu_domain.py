@@ -108,3 +108,21 @@ def test_domain_max_size_sampled(cvf, oracle_mod, L):
     ch.close()
     del ch
     torch.cuda.empty_cache()
+
+
+def test_domain_step_limit_and_zero_sweeps(cvf, oracle_mod):
+    """cvf_set_stop stops the arm-domain sweep exactly at its step; zero
+    sweeps change nothing."""
+    op = oracle_mod.params_from_si(300.0, 25.0, L=21, seed=620)
+    ch = cvf.Chain(gpu_params(cvf, op), cvf.CVF_ALGO_METROPOLIS)
+    ch.metropolis_domain(0)
+    assert ch.obs()["step"] == 0
+    ch.set_stop(5)
+    ch.metropolis_domain(9)                       # 4 of them are skipped
+    oc = oracle_mod.Chain(op).metropolis_domain(5)
+    og, oo = ch.obs(), oc.obs()
+    assert og["step"] == 5 and og["met_attempted"] == oo["met_attempted"] == 4 * 21 * 21 * 5
+    assert np.array_equal(ch.sigma.cpu().numpy(), oc.sigma())
+    for k in ("n_hb_raw", "n_coop", "count", "met_accepted", "vol_accepted"):
+        assert og[k] == oo[k], k
+    ch.close()
