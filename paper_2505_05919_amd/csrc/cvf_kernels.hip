@@ -374,15 +374,18 @@ hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)
 template <int Q>
 void launch_domain_q(const LatticeArgs& a, uint32_t pass, dim3 grid, uint32_t rows, hipStream_t s)
 {
-    if (a.L % 2 == 0) met_domain_kernel<Q, true><<<grid, 256, 0, s>>>(a, pass, rows);
-    else met_domain_kernel<Q, false><<<grid, 256, 0, s>>>(a, pass, rows);
+    if (a.L % 4 == 0) met_domain_kernel<Q, 2><<<grid, 256, 0, s>>>(a, pass, rows);
+    else if (a.L % 2 == 0) met_domain_kernel<Q, 1><<<grid, 256, 0, s>>>(a, pass, rows);
+    else met_domain_kernel<Q, 0><<<grid, 256, 0, s>>>(a, pass, rows);
 }
 
 hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s)
 {
-    // column pairs, (L + 1) / 2 per row; rows per wavefront for ~8192
-    // wavefronts (measured at L = 4096: 515 vs 458 updates/ns for 4096)
-    const uint32_t groups = ((a.L + 1) / 2 + 63) / 64;
+    // lanes own column quads (L % 4 == 0) or pairs, (L + 1) / 2 per row; rows
+    // per wavefront for ~8192 wavefronts (measured at L = 4096 with pairs:
+    // 515 vs 458 updates/ns for 4096)
+    const uint32_t lanes = (a.L % 4 == 0) ? a.L / 4 : (a.L + 1) / 2;
+    const uint32_t groups = (lanes + 63) / 64;
     const uint32_t wpg = groups >= 8192 ? 1 : 8192 / groups;
     const uint32_t rows = min(32u, (a.L + wpg - 1) / wpg);
     const dim3 grid(groups, ((a.L + rows - 1) / rows + 3) / 4);

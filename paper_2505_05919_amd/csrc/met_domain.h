@@ -96,7 +96,68 @@ __device__ __forceinline__ uint32_t dom_rows(const LatticeArgs& a, const uint2* 
     return wsum;
 }
 
-template <int Q, bool EVEN>
+// The rows of one wavefront for pass ARM when L % 4 == 0: lane j owns the
+// quad of columns 4j..4j+3 (two column pairs, two Philox blocks) and moves
+// whole dwords: the four planes, the facing bytes (the same dwords and one
+// edge byte for arms 0 and 1, one dword of the neighbour row for arms 2 and
+// 3), one dword store of the moved plane.
+template <int Q, int ARM>
+__device__ __forceinline__ uint32_t dom_rows_quad(const LatticeArgs& a, const uint2* tbl, uint32_t t, uint32_t j,
+                                                  uint32_t y0, uint32_t y1)
+{
+    constexpr int B1 = ARM == 0 ? 1 : 0, B2 = ARM <= 1 ? 2 : 1, B3 = ARM == 3 ? 2 : 3;   // the other arms
+    const uint32_t L = a.L, N = a.N, np = L >> 1;
+    const uint32_t x4 = 4 * j;
+    const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 == L) ? 0 : x4 + 4;
+    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * N);
+    const uint32_t ap = ARM * N;
+    uint32_t wsum = 0;
+    for (uint32_t y = y0; y < y1; ++y) {
+        const uint32_t o = y * L;
+        uint32_t D[4];
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) D[b] = ld32(rs, x4, b * N + o) << 2;   // bytes hold 4 sigma
+        uint32_t f[4];
+        if (ARM == 0) {
+            f[0] = byte4<1>(D[1]);
+            f[1] = byte4<2>(D[1]);
+            f[2] = byte4<3>(D[1]);
+            f[3] = ld8(rs, xr, N + o) << 2;
+        } else if (ARM == 1) {
+            f[0] = ld8(rs, xl, o) << 2;
+            f[1] = byte4<0>(D[0]);
+            f[2] = byte4<1>(D[0]);
+            f[3] = byte4<2>(D[0]);
+        } else {
+            const uint32_t fy = (ARM == 2) ? ((y + 1 == L) ? 0 : y + 1) : ((y == 0) ? L - 1 : y - 1);
+            const uint32_t F = ld32(rs, x4, (ARM ^ 1) * N + fy * L) << 2;
+            f[0] = byte4<0>(F);
+            f[1] = byte4<1>(F);
+            f[2] = byte4<2>(F);
+            f[3] = byte4<3>(F);
+        }
+        const uint4 wa = philox(2 * j + np * y, t, ARM, kStreamDom, a.key0, a.key1);
+        const uint4 wb = philox(2 * j + 1 + np * y, t, ARM, kStreamDom, a.key0, a.key1);
+        uint32_t s[4];
+#define CVF_DOM_CELL(K, W0, W1)                                                                             \
+        {                                                                                                   \
+            s[K] = byte4<K>(D[ARM]);                                                                        \
+            const uint32_t z = (1u << byte4<K>(D[B1])) + (1u << byte4<K>(D[B2])) + (1u << byte4<K>(D[B3])) + \
+                               (8u << f[K]);                                                                \
+            met_arm<Q>(s[K], z, W0, W1, tbl, wsum);                                                         \
+        }
+        CVF_DOM_CELL(0, wa.x, wa.y)
+        CVF_DOM_CELL(1, wa.z, wa.w)
+        CVF_DOM_CELL(2, wb.x, wb.y)
+        CVF_DOM_CELL(3, wb.z, wb.w)
+#undef CVF_DOM_CELL
+        st32(rs, (s[0] >> 2) | ((s[1] >> 2) << 8) | ((s[2] >> 2) << 16) | ((s[3] >> 2) << 24), x4, ap + o);
+    }
+    return wsum;
+}
+
+// MODE 0: column pairs, odd L; 1: column pairs, L % 4 == 2; 2: quads, L % 4 == 0.
+template <int Q, int MODE>
 __global__ __launch_bounds__(256) void met_domain_kernel(LatticeArgs a, uint32_t pass, uint32_t rows)
 {
     const int skip = a.st->skip, theta = a.st->theta;
@@ -104,20 +165,22 @@ __global__ __launch_bounds__(256) void met_domain_kernel(LatticeArgs a, uint32_t
     if (skip) return;                                      // step limit reached
     __shared__ uint2 tbl[32];
     const uint32_t arm = __builtin_amdgcn_readfirstlane(domain_arm(a, t, pass));
-    const uint32_t L = a.L, np = (L + 1) >> 1;
+    const uint32_t L = a.L;
+    const uint32_t lanes = MODE == 2 ? (L >> 2) : ((L + 1) >> 1);    // quads or pairs per row
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t pr = blockIdx.x * 64 + lane;
+    const uint32_t j = blockIdx.x * 64 + lane;
     const uint32_t y0 = (blockIdx.y * 4 + wave) * rows;
     met_table(a, tbl, theta);
     uint32_t wsum = 0;
-    if (pr < np && y0 < L) {
+    if (j < lanes && y0 < L) {
         const uint32_t y1 = min(y0 + rows, L);
+        constexpr bool EVEN = MODE != 0;
         switch (arm) {                                     // wave-uniform
-        case 0: wsum = dom_rows<Q, EVEN, 0>(a, tbl, t, pr, y0, y1); break;
-        case 1: wsum = dom_rows<Q, EVEN, 1>(a, tbl, t, pr, y0, y1); break;
-        case 2: wsum = dom_rows<Q, EVEN, 2>(a, tbl, t, pr, y0, y1); break;
-        default: wsum = dom_rows<Q, EVEN, 3>(a, tbl, t, pr, y0, y1); break;
+        case 0: wsum = MODE == 2 ? dom_rows_quad<Q, 0>(a, tbl, t, j, y0, y1) : dom_rows<Q, EVEN, 0>(a, tbl, t, j, y0, y1); break;
+        case 1: wsum = MODE == 2 ? dom_rows_quad<Q, 1>(a, tbl, t, j, y0, y1) : dom_rows<Q, EVEN, 1>(a, tbl, t, j, y0, y1); break;
+        case 2: wsum = MODE == 2 ? dom_rows_quad<Q, 2>(a, tbl, t, j, y0, y1) : dom_rows<Q, EVEN, 2>(a, tbl, t, j, y0, y1); break;
+        default: wsum = MODE == 2 ? dom_rows_quad<Q, 3>(a, tbl, t, j, y0, y1) : dom_rows<Q, EVEN, 3>(a, tbl, t, j, y0, y1); break;
         }
     }
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);

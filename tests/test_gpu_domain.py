@@ -1,8 +1,8 @@
 """GPU parity of the arm-domain Metropolis sweep (the paper's layered
 partition, Sec. II.C) against the oracle, through the C ABI: bond indices and
 every counter bit for bit after each block of sweeps, on even and odd
-lattices (one-cell last pairs, the 16-bit even-L path, several workgroup
-tiles and ragged tails), mixed with checkerboard sweeps and Swendsen-Wang
+lattices (one-cell last pairs, the 16-bit pair path for L % 4 == 2, the
+quad path for L % 4 == 0, several workgroup tiles and ragged tails), mixed with checkerboard sweeps and Swendsen-Wang
 steps on even L; odd L rejected by the checkerboard, SW and batch entry
 points; and the largest odd and even lattices on sampled cells.
 """
@@ -65,7 +65,7 @@ def nbr(L, x, y, a):
     return [((x + 1) % L, y), ((x - 1) % L, y), (x, (y + 1) % L), (x, (y - 1) % L)][a]
 
 
-@pytest.mark.parametrize("L", [32765, 32766])
+@pytest.mark.parametrize("L", [32764, 32765, 32766])
 def test_domain_max_size_sampled(cvf, oracle_mod, L):
     """One sweep at the largest sizes, without the volume move: a sampled
     cell after pass k is rebuilt from its own state and its facing
