@@ -203,20 +203,27 @@ def bench_served(torch, n_jobs):
     T ~ U(270, 330) K, P ~ U(0, 50) MPa, nsteps ~ U[100, 10^4], 80 % Metropolis /
     20 % SW, admitted by HBM footprint, lattices resident; p50/p99 latency next
     to throughput, against a one-job-at-a-time FCFS server with plain launches
-    on the same trace (service times measured job by job)."""
+    on the same trace (service times measured job by job).  Quanta advance the
+    jobs with the least remaining work first (until they hold 2^24 cells); the
+    same trace under processor sharing (every resident job in every quantum)
+    is reported beside it."""
     from paper_2505_05919_amd import serve
     from paper_2505_05919_amd.workloads import c5_stream
     jobs = c5_stream(n_jobs=n_jobs)
-    srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True)
+    ps = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="all")
+    s_ps = serve.summarize(ps.run(jobs, realtime=True))
+    srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="srpt",
+                       fill_cells=1 << 24)
     recs = srv.run(jobs, realtime=True)
     s = serve.summarize(recs)
+    ps_digest = {r.job.seed: r.digest for r in ps.records}
     by_seed = {r.job.seed: r for r in recs}
     service, same = [], True
     for j in jobs:
         o, dg, dt = serve.run_alone(j)
         service.append(dt)
         r = by_seed[j.seed]
-        same = same and r.digest == dg and r.obs == o
+        same = same and r.digest == dg and r.obs == o and ps_digest[j.seed] == dg
     lat = serve.fcfs_latencies(jobs, service)
     span_alone = max(max(j.arrival for j in jobs), 0.0)
     done = 0.0
@@ -225,6 +232,9 @@ def bench_served(torch, n_jobs):
     upd = sum(4 * j.L ** 2 * j.nsteps for j in jobs if j.algo == "met")
     offered = upd / max(j.arrival for j in jobs) / 1e9
     return {"jobs": n_jobs, "rate_per_s": 200.0, "quantum": srv.quantum,
+            "schedule": "least remaining work first, >= 2^24 cells per quantum",
+            "processor_sharing": {"p50_ms": round(s_ps["p50_s"] * 1e3, 1), "p99_ms": round(s_ps["p99_s"] * 1e3, 1),
+                                  "makespan_s": round(s_ps["makespan_s"], 3)},
             "p50_ms": round(s["p50_s"] * 1e3, 1), "p99_ms": round(s["p99_s"] * 1e3, 1),
             "queue_p50_ms": round(s["queue_p50_s"] * 1e3, 1), "queue_p99_ms": round(s["queue_p99_s"] * 1e3, 1),
             "makespan_s": round(s["makespan_s"], 3), "met_updates_per_ns": round(s["met_updates_per_ns"], 1),

@@ -69,6 +69,13 @@ class Server:
     graph_block: int = 0                # >0: batched sweeps replay a hipGraph of this many
     keep_digest: bool = False
     policy: AlgoPolicy | None = None    # algorithm choice at arrival (None: as submitted)
+    # quantum membership: "all" advances every resident job (processor
+    # sharing); "srpt" advances the resident jobs with the least remaining
+    # work first, adding jobs (per algorithm) until a quantum holds at least
+    # fill_cells lattice cells, so short jobs finish early while the batch
+    # still fills the GPU
+    schedule: str = "all"
+    fill_cells: int = 1 << 24
     records: list = field(default_factory=list)
     peak_resident_bytes: int = 0
     peak_resident_jobs: int = 0
@@ -77,6 +84,11 @@ class Server:
     # the quantum's launches (and batch rebuilds), waiting for the GPU, retiring
     # finished jobs (observables, digests)
     phase_s: dict = field(default_factory=lambda: {"admit": 0.0, "launch": 0.0, "wait": 0.0, "retire": 0.0})
+
+    def _members(self, runs: list) -> list:
+        if self.schedule == "srpt":
+            return _srpt(runs, self.fill_cells)
+        return runs
 
     def run(self, jobs: list[Job], realtime: bool = True) -> list[Record]:
         """Serve `jobs` (sorted by arrival).  realtime: arrivals are released
@@ -126,8 +138,8 @@ class Server:
                 continue
             tq = time.perf_counter()
             self.phase_s["admit"] += tq - tp
-            met = [r for r in running if r.job.algo == "met"]
-            sws = [r for r in running if r.job.algo == "sw"]
+            met = self._members([r for r in running if r.job.algo == "met"])
+            sws = self._members([r for r in running if r.job.algo == "sw"])
             # one quantum: every resident job advances by min(quantum, remaining) steps
             if met:
                 steps = min(self.quantum, max(r.job.nsteps - r.done for r in met))
@@ -185,6 +197,22 @@ class Server:
         if swb is not None:
             swb.close()
         return self.records
+
+
+def _remaining_work(r: Running) -> int:
+    return (r.job.nsteps - r.done) * r.job.L * r.job.L
+
+
+def _srpt(runs: list, fill_cells: int) -> list:
+    """The runs with the least remaining work, until they hold fill_cells
+    cells per step."""
+    out, cells = [], 0
+    for r in sorted(runs, key=lambda r: (_remaining_work(r), r.job.seed)):
+        out.append(r)
+        cells += r.job.L * r.job.L
+        if cells >= fill_cells:
+            break
+    return out
 
 
 def run_alone(job: Job) -> tuple[dict, str, float]:

@@ -80,3 +80,17 @@ def test_served_with_algorithm_policies(serve):
     assert set(table) == {205.0, 300.0}
     pol = AlgoPolicy("cost", table=table)
     assert {pol.choose(j) for j in jobs} <= {"met", "sw"}
+
+
+def test_served_least_remaining_work_first(serve):
+    """The srpt schedule (a subset of resident jobs per quantum) changes
+    latencies, never results: every job equals the same job run alone."""
+    jobs = small_stream(20)
+    srv = serve.Server(memory_budget=1 << 34, max_slots=32, quantum=6, keep_digest=True, schedule="srpt",
+                       fill_cells=3000)
+    recs = srv.run(jobs, realtime=True)
+    assert len(recs) == len(jobs)
+    by_seed = {r.job.seed: r for r in recs}
+    for j in jobs:
+        o, dg, _ = serve.run_alone(j)
+        assert by_seed[j.seed].digest == dg and by_seed[j.seed].obs == o, j
