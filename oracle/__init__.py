@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cvf_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "cvf3_oracle.c")]
 _LIB = os.path.join(_HERE, "libcvf_oracle.so")
 
 INIT, VOL, MET, SWB, SWF = 0, 1, 2, 3, 4
@@ -27,9 +28,11 @@ NO_VOLUME_MOVE = 1
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS + [os.path.join(_HERE, "cvf_oracle.h"),
+                                                       os.path.join(_HERE, "cvf3_oracle.h")])
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-fPIC", "-shared", *_SRCS, "-o", _LIB + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
