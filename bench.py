@@ -118,6 +118,45 @@ def bench_autocorr(torch, cvf, L=256, points=((270.0, 7), (300.0, 9))):
     return out
 
 
+ALU_OPS_3D = 39      # half a Philox block (20) + decision over five other arms (18) + eta gate (1)
+BYTES_3D = 9         # six own bond indices + facing one + the edge's eta read, one written
+
+
+def bench_cvf3(torch, W, K, L=260):
+    """The paper's own model and size: cubic lattice with eta, N = 260^3, one
+    step = volume move + eta moves + six arm-domain passes (Sec. II.B-C)."""
+    from paper_2505_05919_amd import cvf, cvf3
+    p = cvf.cvf_params_from_si(300.0, 0.1, L=L, seed=2026)
+    ch = cvf3.Chain3(p)
+    N = L ** 3
+    ch.steps(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.steps(K)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cvf3.cvf3_timing_enable(ch.h, True)
+    ch.steps(K)
+    kt = {k: cvf3.cvf3_kernel_times(ch.h, k) for k in (cvf3.CVF3_K_VOLUME, cvf3.CVF3_K_ETA, cvf3.CVF3_K_PASS)}
+    cvf3.cvf3_timing_enable(ch.h, False)
+    o = ch.obs()
+    assert o["consistent"] == 1 and o["n_eta0"] == N
+    ch.close()
+    pass_s = kt[cvf3.CVF3_K_PASS][1] * 1e-3
+    gbs = N * BYTES_3D / pass_s / 1e9
+    tops = N * ALU_OPS_3D / pass_s / 1e12
+    return {"L": L, "N": N, "steps": K, "ms_per_step": round(t / K * 1e3, 4),
+            "updates_per_ns": round(6 * N * K / t / 1e9, 2),
+            "kernel_mean_us": {"volume": round(kt[cvf3.CVF3_K_VOLUME][1] * 1e3, 2),
+                               "eta": round(kt[cvf3.CVF3_K_ETA][1] * 1e3, 2),
+                               "pass": round(kt[cvf3.CVF3_K_PASS][1] * 1e3, 2)},
+            "pass_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": BYTES_3D,
+                              "alu": {"achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                                      "frac": round(tops / VALU_PEAK_TOPS, 4), "ops_per_update": ALU_OPS_3D}},
+            "paper_rtx3060_ms_per_step": 280.0}
+
+
 def cpu_baseline(budget_s: float):
     """The oracle as it stands (single thread), Metropolis on the headline
     lattice, sweeps until the budget is used."""
@@ -262,6 +301,8 @@ def main():
     ap.add_argument("--skip-domain", action="store_true")
     ap.add_argument("--skip-autocorr", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-cvf3", action="store_true")
+    ap.add_argument("--cvf3-steps", type=int, default=200)
     ap.add_argument("--batch-sweeps", type=int, default=1000)
     ap.add_argument("--serve-jobs", type=int, default=120,
                     help="jobs of the served Poisson stream (0 = skip)")
@@ -388,6 +429,13 @@ def main():
             ch.close()
         del dch
 
+    # ---------------- cubic lattice with eta, N = 260^3 ----------------
+    c3 = None
+    if not args.skip_cvf3:
+        log(f"cubic lattice with eta: L=260, warmup {min(W, 20)}, steps {args.cvf3_steps}")
+        c3 = bench_cvf3(torch, min(W, 20), args.cvf3_steps)
+        log(f"cvf3: {c3}")
+
     # ---------------- autocorrelation and cost per independent configuration ----------------
     auto = None
     if not args.skip_autocorr:
@@ -431,6 +479,7 @@ def main():
                    "L": 4096, "T_K": 300.0, "P_MPa": [0.1, 25.0, 50.0], "q": 6, "seeds": [12, 13, 14]},
         "sw": sw,
         "met_domain": dom,
+        "cvf3": c3,
         "autocorr": auto,
         "batched": batched,
         "served": served,

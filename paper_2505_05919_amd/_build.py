@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcvf.so")
 
-SOURCES = ["cvf_kernels.hip", "cvf_api.cpp"]
+SOURCES = ["cvf_kernels.hip", "cvf_api.cpp", "cvf3.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

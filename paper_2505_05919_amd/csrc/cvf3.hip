@@ -1,0 +1,889 @@
+// CVF water model on the periodic simple-cubic lattice with the eta bond
+// constraint (Sec. II.A-C, App. A): device kernels and the cvf3_* C ABI.
+//
+// One MC step on the caller's stream (Sec. II.B):
+//   vol3_kernel   one workgroup: folds the previous step's per-workgroup
+//                 counter slots, performs the FP64 volume move, draws the
+//                 order of the six arm passes
+//   eta3_kernel   one thread per checkerboard cube: Metropolis move of the
+//                 cube's eta configuration (one of the nine perfect matchings
+//                 of the cube graph marks the eta = 0 edges)
+//   pass3_kernel  x6, one per arm in the drawn order: every cell's bond index
+//                 of that arm moves once (the arm-domain partition of
+//                 Sec. II.C); a lane moves two x-adjacent cells, which share
+//                 one Philox block
+// Layout: sigma[a*N + c], eta[d*N + c] (edge from c to its +d neighbour),
+// c = x + L*(y + L*z); arms 0:+x 1:-x 2:+y 3:-y 4:+z 5:-z.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cvf.h"
+#include "cvf3.h"
+
+namespace {
+
+#include "philox.h"
+
+constexpr uint32_t kInit = 0, kVol = 1, kOrd = 5, kDom = 6, kEta = 7;
+constexpr int kSlots = 256;              // counter slots, spread to avoid one hot atomic
+constexpr int kAcc = 4;                  // d N_HB_raw, d N_sigma, sigma accepted, eta accepted
+constexpr int kRc = 10;                  // recount: N_HB_raw, N_sigma, N_q' (6), eta = 0 edges, spare
+constexpr int kBlock = 256;
+
+struct Dev3State {
+    double  v, u;
+    int64_t t_next, t_cur;
+    int64_t n_hb_raw, n_coop;
+    int64_t met_att, met_acc, eta_att, eta_acc, vol_att, vol_acc;
+    int32_t theta, fold_only;
+    int32_t order[6];
+    int32_t pad[2];
+};
+
+struct Tab3 {
+    uint32_t met[2][3][11];   // sigma move: [theta*eta][dh+1][dc+5]
+    uint32_t eta[9];          // eta move in the liquid: [dn+4]
+    uint32_t match[9];        // perfect matchings of the cube graph (12-bit edge masks, eta = 0)
+    uint64_t lim[6];          // lim[i] = i floor(2^32/(q-1)), i = 1..q-1 (uniform pick over q-1)
+    double   r3[40];          // r3(m), m = 0..36
+};
+
+struct Lat3 {
+    uint8_t*   sigma;
+    uint8_t*   eta;
+    Dev3State* st;
+    int64_t*   slots;         // [kAcc][kSlots]
+    int64_t*   rc;            // [kRc][kSlots]
+    const Tab3* tab;          // device copy
+    uint32_t L, N, h, q;
+    uint32_t key0, key1;
+    uint32_t pass;
+    uint32_t pad;
+    double   invL, invH, Nd, beta, J, P, vHB, dv_max;
+    int32_t  do_volume;
+};
+
+__device__ __forceinline__ uint32_t udiv(uint32_t n, uint32_t d, double inv)
+{
+    uint32_t q = (uint32_t)((double)n * inv);
+    const int64_t r = (int64_t)n - (int64_t)q * d;
+    if (r < 0) --q;
+    else if (r >= (int64_t)d) ++q;
+    return q;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sums K per-thread values over the workgroup and adds them to slot
+// (blockIdx % kSlots) of each of K counters (stride kSlots).
+template <int K>
+__device__ void block_slots(int (&v)[K], int64_t* dst)
+{
+    __shared__ int part[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int s = wave_sum(v[k]);
+        if (lane == 0) part[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        int64_t s = 0;
+        for (int i = 0; i < kBlock / 64; ++i) s += part[threadIdx.x][i];
+        if (s) atomicAdd((unsigned long long*)(dst + (size_t)threadIdx.x * kSlots + blockIdx.x % kSlots),
+                         (unsigned long long)s);
+    }
+}
+
+// U_LJ per molecule on the cubic lattice (Sec. II.A): shells m = |n|^2 in
+// ascending order, (distance/r0)^6 = v^2 m^3, cutoff 6^6.
+__device__ __host__ double lj3(double v, const double* r3)
+{
+    double s = 0.0;
+    for (int m = 1; m <= 36; ++m) {
+        const double d6 = (v * v) * (double)(m * m * m);
+        if (!(d6 <= 46656.0)) break;
+        const double s6 = 1.0 / d6;
+        s = s + r3[m] * (s6 * s6 - s6);
+    }
+    return 2.0 * s;
+}
+
+// Uniform draw of {0..k-1} from one word by the exact-block rule (NONE = -1
+// when the word falls in the incomplete top block).
+__device__ __forceinline__ int pick_div(uint32_t w, uint32_t k)
+{
+    const uint32_t d = (uint32_t)(4294967296ull / k);
+    if ((uint64_t)w >= (uint64_t)k * d) return -1;
+    return (int)(w / d);
+}
+
+// Corner vtx (bit 0: +x, 1: +y, 2: +z) of cube k: parity k / h^3 sets the
+// lowest corner (2i+par, 2j+par, 2l+par).
+struct Cube {
+    uint32_t x0, y0, z0;
+};
+
+__device__ __forceinline__ Cube cube_of(const Lat3& a, uint32_t k)
+{
+    const uint32_t h3 = a.h * a.h * a.h;
+    const uint32_t par = k >= h3 ? 1u : 0u;
+    const uint32_t r = k - par * h3;
+    const uint32_t jl = udiv(r, a.h, a.invH);
+    const uint32_t i = r - jl * a.h;
+    const uint32_t l = udiv(jl, a.h, a.invH);
+    const uint32_t j = jl - l * a.h;
+    return {2 * i + par, 2 * j + par, 2 * l + par};
+}
+
+__device__ __forceinline__ uint32_t cell_at(const Lat3& a, const Cube& q, uint32_t vtx)
+{
+    uint32_t x = q.x0 + (vtx & 1), y = q.y0 + ((vtx >> 1) & 1), z = q.z0 + ((vtx >> 2) & 1);
+    x = x == a.L ? 0 : x;
+    y = y == a.L ? 0 : y;
+    z = z == a.L ? 0 : z;
+    return x + a.L * (y + a.L * z);
+}
+
+// Ends of cube edge e: axis d = e / 4, r = e % 4 places it along the two
+// other axes (lower axis in bit 0).
+__device__ __forceinline__ void edge_vtx(int e, uint32_t& lo, uint32_t& hi)
+{
+    const int d = e >> 2, r = e & 3;
+    uint32_t v;
+    if (d == 0) v = ((r & 1) << 1) | ((r >> 1) << 2);
+    else if (d == 1) v = (r & 1) | ((r >> 1) << 2);
+    else v = (r & 1) | ((r >> 1) << 1);
+    lo = v;
+    hi = v | (1u << d);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: sigma of cell c from words 0..3 of Philox(c, 0, 0, INIT) and
+// words 0, 1 of Philox(c, 0, 1, INIT); eta of cube k from configuration
+// pick(word 0 of Philox(k, 0, 2, INIT), 9), NONE -> 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void init3_sigma_kernel(Lat3 a)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.N) return;
+    const uint4 w0 = philox(c, 0u, 0u, kInit, a.key0, a.key1);
+    const uint4 w1 = philox(c, 0u, 1u, kInit, a.key0, a.key1);
+    const uint32_t w[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
+#pragma unroll
+    for (int b = 0; b < 6; ++b) a.sigma[(size_t)b * a.N + c] = (uint8_t)(((uint64_t)w[b] * a.q) >> 32);
+}
+
+__global__ __launch_bounds__(kBlock) void init3_eta_kernel(Lat3 a)
+{
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.N / 4) return;
+    const uint4 w = philox(k, 0u, 2u, kInit, a.key0, a.key1);
+    int m = pick_div(w.x, 9);
+    if (m < 0) m = 0;
+    const uint32_t mask = a.tab->match[m];
+    const Cube q = cube_of(a, k);
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        uint32_t lo, hi;
+        edge_vtx(e, lo, hi);
+        a.eta[(size_t)(e >> 2) * a.N + cell_at(a, q, lo)] = (uint8_t)(((mask >> e) & 1) ^ 1);
+    }
+}
+
+__global__ void state3_init_kernel(Lat3 a, double v_init)
+{
+    for (int i = threadIdx.x; i < kAcc * kSlots; i += blockDim.x) a.slots[i] = 0;
+    if (threadIdx.x == 0) {
+        Dev3State* s = a.st;
+        memset(s, 0, sizeof(*s));
+        s->v = v_init;
+        s->u = lj3(v_init, a.tab->r3);
+        s->theta = v_init < 2.0 ? 1 : 0;
+        for (int i = 0; i < 6; ++i) s->order[i] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Counter fold + volume move (Sec. II.B step 1) + pass order of the step.
+// dH = N (u(v') - u(v)) + P N (v' - v) + (theta' - theta)(P v_HB - J) N_HB_raw
+// with words 0, 1 of Philox(0, t, 0, VOL); order: Fisher-Yates over 0..5
+// with words 0..3 of Philox(0, t, 0, ORD) and word 0 of Philox(0, t, 1, ORD).
+// mode 0: full step opening; mode 1: fold only.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int fold_only)
+{
+    __shared__ int64_t part[kAcc][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t v[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) {
+        v[k] = a.slots[k * kSlots + threadIdx.x];
+        a.slots[k * kSlots + threadIdx.x] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) {
+        int64_t s = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) part[k][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int64_t tot[kAcc];
+    for (int k = 0; k < kAcc; ++k) {
+        tot[k] = 0;
+        for (int i = 0; i < kBlock / 64; ++i) tot[k] += part[k][i];
+    }
+    Dev3State* s = a.st;
+    s->n_hb_raw += tot[0];
+    s->n_coop += tot[1];
+    s->met_acc += tot[2];
+    s->eta_acc += tot[3];
+    if (fold_only) return;
+    const uint32_t t = (uint32_t)s->t_next;
+    if (a.do_volume) {
+        const uint4 w = philox(0u, t, 0u, kVol, a.key0, a.key1);
+        s->vol_att += 1;
+        const double u = (double)((int64_t)2 * (int64_t)w.x + 1 - 4294967296LL) * (1.0 / 4294967296.0);
+        const double v0 = s->v;
+        const double v1 = v0 + a.dv_max * u;
+        if (v1 >= 1.0) {
+            const double u0 = s->u, u1 = lj3(v1, a.tab->r3);
+            const int th0 = s->theta, th1 = v1 < 2.0 ? 1 : 0;
+            const double dH = (a.Nd * (u1 - u0)) + ((a.P * a.Nd) * (v1 - v0))
+                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)s->n_hb_raw);
+            bool acc = dH <= 0.0;
+            if (!acc) acc = ((double)w.y + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
+            if (acc) {
+                s->v = v1;
+                s->u = u1;
+                s->theta = th1;
+                s->vol_acc += 1;
+            }
+        }
+    }
+    const uint4 o0 = philox(0u, t, 0u, kOrd, a.key0, a.key1);
+    const uint4 o1 = philox(0u, t, 1u, kOrd, a.key0, a.key1);
+    const uint32_t ow[5] = {o0.x, o0.y, o0.z, o0.w, o1.x};
+    int ord[6] = {0, 1, 2, 3, 4, 5};
+    for (int i = 0; i < 5; ++i) {
+        int k = pick_div(ow[i], (uint32_t)(6 - i));
+        if (k < 0) k = 0;
+        const int tmp = ord[i];
+        ord[i] = ord[i + k];
+        ord[i + k] = tmp;
+    }
+    for (int i = 0; i < 6; ++i) s->order[i] = ord[i];
+    s->t_cur = t;
+    s->t_next += 1;
+    s->met_att += 6 * (int64_t)a.N;
+    s->eta_att += a.N / 4;
+}
+
+// ---------------------------------------------------------------------------
+// eta update (Sec. II.B step 2, App. A): one thread per cube.  Proposal
+// pick(w0, 9) of Philox(k, t, 0, ETA) (NONE: no move); dn = change of
+// N_HB_raw inside the cube; accepted through the eta table and w1 in the
+// liquid, always in the gas.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void eta3_kernel(Lat3 a)
+{
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    int cnt[2] = {0, 0};
+    if (k < a.N / 4) {
+        const uint32_t t = (uint32_t)a.st->t_cur;
+        const int theta = a.st->theta;
+        const uint4 w = philox(k, t, 0u, kEta, a.key0, a.key1);
+        const int m = pick_div(w.x, 9);
+        if (m >= 0) {
+            const uint32_t mask = a.tab->match[m];
+            const Cube q = cube_of(a, k);
+            uint32_t cell[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) cell[v] = cell_at(a, q, v);
+            int dn = 0;
+            uint32_t old = 0;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                uint32_t lo, hi;
+                edge_vtx(e, lo, hi);
+                const int d = e >> 2;
+                const int eq = a.sigma[(size_t)(2 * d) * a.N + cell[lo]] == a.sigma[(size_t)(2 * d + 1) * a.N + cell[hi]];
+                const int eo = a.eta[(size_t)d * a.N + cell[lo]];
+                old |= (uint32_t)eo << e;
+                const int en = (int)(((mask >> e) & 1) ^ 1);
+                dn += (en - eo) * eq;
+            }
+            bool acc = true;
+            if (theta) {
+                const uint32_t thr = a.tab->eta[dn + 4];
+                acc = thr == 0xFFFFFFFFu || w.y < thr;
+            }
+            if (acc) {
+                cnt[0] = dn;
+                cnt[1] = 1;
+                const uint32_t neu = (~mask) & 0xFFFu;
+                if (neu != old) {
+#pragma unroll
+                    for (int e = 0; e < 12; ++e) {
+                        uint32_t lo, hi;
+                        edge_vtx(e, lo, hi);
+                        if (((neu ^ old) >> e) & 1)
+                            a.eta[(size_t)(e >> 2) * a.N + cell[lo]] = (uint8_t)((neu >> e) & 1);
+                    }
+                }
+            }
+        }
+    }
+    int v4[2] = {cnt[0], cnt[1]};
+    // slots: 0 = d N_HB_raw, 3 = eta accepted
+    __shared__ int part[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j = 0; j < 2; ++j) {
+        const int s = wave_sum(v4[j]);
+        if (lane == 0) part[j][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int64_t s = 0;
+        for (int i = 0; i < kBlock / 64; ++i) s += part[threadIdx.x][i];
+        const int slot = threadIdx.x == 0 ? 0 : 3;
+        if (s) atomicAdd((unsigned long long*)(a.slots + (size_t)slot * kSlots + blockIdx.x % kSlots),
+                         (unsigned long long)s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arm-domain pass (Sec. II.C): arm A of every cell.  Lane = cell pair
+// (2p, 2p+1) of one x-row, Philox(p, t, A, DOM) words 0, 1 for the even cell
+// and 2, 3 for the odd one.  Own bond indices and the aligned facing/eta
+// pairs are 16-bit loads; the x arms' facing and eta pairs straddle the pair
+// and wrap at the row end, so they are byte loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void move_one(const uint32_t* met, const uint64_t* lim, int q, int theta, uint32_t own[6],
+                                         int A, uint32_t facing, uint32_t eta, uint32_t prop, uint32_t accw,
+                                         int& dhb, int& dco, int& nacc)
+{
+    if ((uint64_t)prop >= lim[q - 1]) return;            // NONE
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) k += (i < q - 1 && (uint64_t)prop >= lim[i]) ? 1 : 0;
+    const uint32_t old = own[A];
+    uint32_t neu = old + 1 + (uint32_t)k;
+    neu = neu >= (uint32_t)q ? neu - (uint32_t)q : neu;
+    const int dh = (int)(neu == facing) - (int)(old == facing);
+    int dc = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if (b != A) dc += (int)(neu == own[b]) - (int)(old == own[b]);
+    const int th = (theta && eta) ? 1 : 0;
+    const uint32_t thr = met[th * 33 + (dh + 1) * 11 + dc + 5];
+    if (thr == 0xFFFFFFFFu || accw < thr) {
+        own[A] = neu;
+        dhb += (int)eta * dh;
+        dco += dc;
+        nacc += 1;
+    }
+}
+
+template <int A>
+__device__ __forceinline__ void pass_pair(const Lat3& a, const uint32_t* met, const uint64_t* lim, uint32_t p,
+                                          uint32_t t, int theta, int (&cnt)[3])
+{
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t c0 = 2 * p;
+    uint32_t own0[6], own1[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const uint32_t v = *(const uint16_t*)(a.sigma + (size_t)b * N + c0);
+        own0[b] = v & 0xFFu;
+        own1[b] = v >> 8;
+    }
+    uint32_t f0, f1, e0, e1, o = 0;
+    if (A == 0 || A == 1) {
+        const uint32_t yz = udiv(c0, L, a.invL);
+        const uint32_t x0 = c0 - yz * L;
+        if (A == 0) {                                     // facing: arm 1 of x0+1, x0+2
+            const uint32_t r2 = x0 + 2 == L ? c0 + 2 - L : c0 + 2;
+            f0 = a.sigma[(size_t)N + c0 + 1];
+            f1 = a.sigma[(size_t)N + r2];
+            const uint32_t ee = *(const uint16_t*)(a.eta + c0);
+            e0 = ee & 0xFFu;
+            e1 = ee >> 8;
+        } else {                                          // facing: arm 0 of x0-1, x0
+            const uint32_t l1 = x0 == 0 ? c0 + L - 1 : c0 - 1;
+            f0 = a.sigma[l1];
+            f1 = a.sigma[c0];
+            e0 = a.eta[l1];
+            e1 = a.eta[c0];
+        }
+    } else {
+        const uint32_t L2 = L * L;
+        if (A == 2 || A == 3) {
+            const uint32_t yz = udiv(c0, L, a.invL);
+            const uint32_t z = udiv(yz, L, a.invL);
+            const uint32_t y = yz - z * L;
+            if (A == 2) o = y == L - 1 ? c0 + L - L2 : c0 + L;
+            else o = y == 0 ? c0 + L2 - L : c0 - L;
+        } else if (A == 4) {
+            o = c0 + L2 >= N ? c0 + L2 - N : c0 + L2;
+        } else {
+            o = c0 >= L2 ? c0 - L2 : c0 + N - L2;
+        }
+        const uint32_t ff = *(const uint16_t*)(a.sigma + (size_t)(A ^ 1) * N + o);
+        f0 = ff & 0xFFu;
+        f1 = ff >> 8;
+        const uint32_t ee = *(const uint16_t*)(a.eta + (size_t)(A >> 1) * N + ((A & 1) ? o : c0));
+        e0 = ee & 0xFFu;
+        e1 = ee >> 8;
+    }
+    const uint4 w = philox(p, t, (uint32_t)A, kDom, a.key0, a.key1);
+    const uint32_t old0 = own0[A], old1 = own1[A];
+    move_one(met, lim, (int)a.q, theta, own0, A, f0, e0, w.x, w.y, cnt[0], cnt[1], cnt[2]);
+    move_one(met, lim, (int)a.q, theta, own1, A, f1, e1, w.z, w.w, cnt[0], cnt[1], cnt[2]);
+    if (own0[A] != old0 || own1[A] != old1)
+        *(uint16_t*)(a.sigma + (size_t)A * N + c0) = (uint16_t)(own0[A] | (own1[A] << 8));
+}
+
+__global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
+{
+    __shared__ uint32_t met[66];
+    __shared__ uint64_t lim[6];
+    if (threadIdx.x < 66) met[threadIdx.x] = (&a.tab->met[0][0][0])[threadIdx.x];
+    if (threadIdx.x < 6) lim[threadIdx.x] = a.tab->lim[threadIdx.x];
+    const int arm = a.st->order[a.pass];
+    const uint32_t t = (uint32_t)a.st->t_cur;
+    const int theta = a.st->theta;
+    __syncthreads();
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    int cnt[3] = {0, 0, 0};
+    if (p < a.N / 2) {
+        switch (arm) {
+        case 0: pass_pair<0>(a, met, lim, p, t, theta, cnt); break;
+        case 1: pass_pair<1>(a, met, lim, p, t, theta, cnt); break;
+        case 2: pass_pair<2>(a, met, lim, p, t, theta, cnt); break;
+        case 3: pass_pair<3>(a, met, lim, p, t, theta, cnt); break;
+        case 4: pass_pair<4>(a, met, lim, p, t, theta, cnt); break;
+        default: pass_pair<5>(a, met, lim, p, t, theta, cnt); break;
+        }
+    }
+    block_slots<3>(cnt, a.slots);                     // slots 0, 1, 2
+}
+
+// ---------------------------------------------------------------------------
+// Full recount of the configuration (observables): N_HB_raw (eta = 1 edges
+// with equal facing sigma), N_sigma (15 pairs per cell), N_q', eta = 0 edges.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void recount3_kernel(Lat3 a)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    int v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < a.N) {
+        const uint32_t L = a.L, N = a.N, L2 = L * L;
+        const uint32_t yz = udiv(c, L, a.invL);
+        const uint32_t x = c - yz * L;
+        const uint32_t z = udiv(yz, L, a.invL);
+        const uint32_t y = yz - z * L;
+        uint32_t s[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) s[b] = a.sigma[(size_t)b * N + c];
+        const uint32_t nbr[3] = {x == L - 1 ? c + 1 - L : c + 1, y == L - 1 ? c + L - L2 : c + L,
+                                 c + L2 >= N ? c + L2 - N : c + L2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t e = a.eta[(size_t)d * N + c];
+            v[0] += (e != 0 && s[2 * d] == a.sigma[(size_t)(2 * d + 1) * N + nbr[d]]) ? 1 : 0;
+            v[8] += e == 0 ? 1 : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) v[1] += s[i] == s[j] ? 1 : 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[2 + k] += s[b] == (uint32_t)k ? 1 : 0;
+    }
+    block_slots<9>(v, a.rc);
+}
+
+__global__ void zero_kernel(int64_t* p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+inline unsigned blocks_for(uint64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ===========================================================================
+// Host side: the cvf3_* C ABI.
+// ===========================================================================
+struct cvf3_state {
+    cvf_params p;
+    Lat3       la;
+    Tab3       htab;
+    Tab3*      dtab;
+    uint8_t*   sigma;
+    uint8_t*   eta;
+    bool       timing;
+    std::vector<hipEvent_t> ev[CVF3_K_COUNT];
+    int64_t    launches[CVF3_K_COUNT];
+    double     total_ms[CVF3_K_COUNT];
+};
+
+namespace {
+
+size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t ws3_bytes() { return al256(sizeof(Dev3State)) + al256(sizeof(int64_t) * kAcc * kSlots) +
+                            al256(sizeof(int64_t) * kRc * kSlots) + al256(sizeof(Tab3)); }
+
+// r3(m): integer points on the sphere i^2 + j^2 + k^2 = m, counted as
+// octant points with signs (each nonzero coordinate doubles the count).
+double sphere_points(int m)
+{
+    int n = 0;
+    for (int i = 0; i * i <= m; ++i)
+        for (int j = 0; i * i + j * j <= m; ++j)
+            for (int k = 0; i * i + j * j + k * k <= m; ++k)
+                if (i * i + j * j + k * k == m) n += (i ? 2 : 1) * (j ? 2 : 1) * (k ? 2 : 1);
+    return (double)n;
+}
+
+uint32_t thr_of(double beta, double dH)
+{
+    if (!(dH > 0.0)) return 0xFFFFFFFFu;
+    const double acc = exp(-beta * dH);
+    if (acc >= 1.0) return 0xFFFFFFFFu;
+    const double f = floor(acc * 4294967296.0);
+    return f > 4294967294.0 ? 0xFFFFFFFEu : (uint32_t)f;
+}
+
+// Perfect matchings of the cube graph, built from its structure: the three
+// one-axis matchings (four parallel edges), and for each axis d the two
+// faces perpendicular to d each taking one of their two non-d matchings
+// where the two faces differ (2 x 3 = 6), sorted by edge mask.
+void cube_matchings(uint32_t out[9])
+{
+    // edge index of the edge along axis d whose other coordinates are (o1, o2)
+    auto edge = [](int d, int o_lo, int o_hi) { return 4 * d + o_lo + 2 * o_hi; };
+    std::vector<uint32_t> ms;
+    for (int d = 0; d < 3; ++d) ms.push_back(0xFu << (4 * d));
+    for (int d = 0; d < 3; ++d) {
+        const int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;   // the two other axes, a1 < a2
+        // face at coordinate s along d: a 4-cycle, matched along a1 or a2
+        for (int f0 = 0; f0 < 2; ++f0) {
+            const int f1 = 1 - f0;
+            uint32_t m = 0;
+            for (int s = 0; s < 2; ++s) {
+                const int along = (s == 0 ? f0 : f1) ? a2 : a1;   // axis of this face's two edges
+                // the edge along `along` has its d coordinate = s and the remaining axis r in {0,1}
+                const int r = 3 - d - along;
+                for (int rv = 0; rv < 2; ++rv) {
+                    int coord[3] = {0, 0, 0};
+                    coord[d] = s;
+                    coord[r] = rv;
+                    int o[2], n = 0;
+                    for (int ax = 0; ax < 3; ++ax)
+                        if (ax != along) o[n++] = coord[ax];
+                    m |= 1u << edge(along, o[0], o[1]);
+                }
+            }
+            ms.push_back(m);
+        }
+    }
+    for (size_t i = 0; i < ms.size(); ++i)
+        for (size_t j = i + 1; j < ms.size(); ++j)
+            if (ms[j] < ms[i]) std::swap(ms[i], ms[j]);
+    for (int i = 0; i < 9; ++i) out[i] = ms[i];
+}
+
+void build_tab3(const cvf_params* p, Tab3* t)
+{
+    memset(t, 0, sizeof(*t));
+    const double Jeff = p->J - p->P * p->vHB;
+    for (int th = 0; th < 2; ++th)
+        for (int dh = -1; dh <= 1; ++dh)
+            for (int dc = -5; dc <= 5; ++dc)
+                t->met[th][dh + 1][dc + 5] = thr_of(p->beta, -((double)th * Jeff * (double)dh) - p->Jsigma * (double)dc);
+    for (int dn = -4; dn <= 4; ++dn) t->eta[dn + 4] = thr_of(p->beta, -(Jeff * (double)dn));
+    cube_matchings(t->match);
+    const uint64_t d = 4294967296ull / (uint64_t)(p->q - 1);
+    for (int i = 0; i < 6; ++i) t->lim[i] = (uint64_t)i * d;
+    for (int m = 0; m < 40; ++m) t->r3[m] = m <= 36 ? sphere_points(m) : 0.0;
+}
+
+int hs(hipError_t e) { return e == hipSuccess ? CVF_OK : CVF_EHIP; }
+
+int validate3(const cvf_params* p)
+{
+    if (!p) return CVF_EINVAL;
+    if (p->L < 2 || p->L > CVF3_MAX_L || (p->L & 1)) return CVF_EINVAL;
+    if (p->q < 2 || p->q > 6) return CVF_EINVAL;
+    if (!(p->beta >= 0.0) || !std::isfinite(p->beta)) return CVF_EINVAL;
+    if (!std::isfinite(p->J) || !std::isfinite(p->Jsigma) || !std::isfinite(p->P) || !std::isfinite(p->vHB))
+        return CVF_EINVAL;
+    if (!(p->v_init >= 1.0) || !std::isfinite(p->v_init)) return CVF_EINVAL;
+    if (!(p->dv_max >= 0.0) || !std::isfinite(p->dv_max)) return CVF_EINVAL;
+    if (p->flags & ~(uint32_t)(CVF_NO_VOLUME_MOVE | CVF_KEEP_SIGMA)) return CVF_EINVAL;
+    if (p->reserved != 0) return CVF_EINVAL;
+    return CVF_OK;
+}
+
+void t_begin(cvf3_state* st, int kind, hipStream_t s)
+{
+    if (!st->timing) return;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return;
+    }
+    (void)hipEventRecord(e0, s);
+    st->ev[kind].push_back(e0);
+    st->ev[kind].push_back(e1);
+}
+
+void t_end(cvf3_state* st, int kind, hipStream_t s)
+{
+    if (!st->timing || st->ev[kind].empty()) return;
+    (void)hipEventRecord(st->ev[kind].back(), s);
+}
+
+int drain3(cvf3_state* st)
+{
+    int rc = CVF_OK;
+    for (int k = 0; k < CVF3_K_COUNT; ++k) {
+        std::vector<hipEvent_t>& v = st->ev[k];
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventSynchronize(v[i + 1]) != hipSuccess || hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
+                rc = CVF_EHIP;
+            st->launches[k] += 1;
+            st->total_ms[k] += ms;
+        }
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cvf3_workspace_bytes(const cvf_params* p, size_t* bytes)
+{
+    if (!bytes) return CVF_EINVAL;
+    const int rc = validate3(p);
+    if (rc != CVF_OK) return rc;
+    *bytes = ws3_bytes();
+    return CVF_OK;
+}
+
+int cvf3_tables(const cvf_params* p, uint32_t met[2][3][11], uint32_t eta[9], uint32_t match[9])
+{
+    if (!met || !eta || !match) return CVF_EINVAL;
+    const int rc = validate3(p);
+    if (rc != CVF_OK) return rc;
+    Tab3 t;
+    build_tab3(p, &t);
+    memcpy(met, t.met, sizeof(t.met));
+    memcpy(eta, t.eta, sizeof(t.eta));
+    memcpy(match, t.match, sizeof(t.match));
+    return CVF_OK;
+}
+
+int cvf3_init(const cvf_params* p, uint8_t* d_sigma, uint8_t* d_eta, void* d_work, size_t work_bytes, void* stream,
+              cvf3_state** out)
+{
+    if (!out) return CVF_EINVAL;
+    *out = nullptr;
+    int rc = validate3(p);
+    if (rc != CVF_OK) return rc;
+    if (!d_sigma || !d_eta || !d_work) return CVF_EINVAL;
+    if (((uintptr_t)d_sigma & 3) || ((uintptr_t)d_eta & 3) || ((uintptr_t)d_work & 255)) return CVF_EINVAL;
+    if (work_bytes < ws3_bytes()) return CVF_ENOMEM;
+    cvf3_state* st = new (std::nothrow) cvf3_state();
+    if (!st) return CVF_ENOMEM;
+    st->p = *p;
+    st->sigma = d_sigma;
+    st->eta = d_eta;
+    build_tab3(p, &st->htab);
+    uint8_t* w = (uint8_t*)d_work;
+    Lat3& a = st->la;
+    a.sigma = d_sigma;
+    a.eta = d_eta;
+    a.st = (Dev3State*)w;
+    w += al256(sizeof(Dev3State));
+    a.slots = (int64_t*)w;
+    w += al256(sizeof(int64_t) * kAcc * kSlots);
+    a.rc = (int64_t*)w;
+    w += al256(sizeof(int64_t) * kRc * kSlots);
+    st->dtab = (Tab3*)w;
+    a.tab = st->dtab;
+    a.L = (uint32_t)p->L;
+    a.N = a.L * a.L * a.L;
+    a.h = a.L / 2;
+    a.q = (uint32_t)p->q;
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.invL = 1.0 / (double)a.L;
+    a.invH = 1.0 / (double)a.h;
+    a.Nd = (double)a.N;
+    a.beta = p->beta;
+    a.J = p->J;
+    a.P = p->P;
+    a.vHB = p->vHB;
+    a.dv_max = p->dv_max;
+    a.do_volume = (p->flags & CVF_NO_VOLUME_MOVE) ? 0 : 1;
+    hipStream_t s = (hipStream_t)stream;
+    rc = hs(hipMemcpyAsync(st->dtab, &st->htab, sizeof(Tab3), hipMemcpyHostToDevice, s));
+    if (rc == CVF_OK) {
+        state3_init_kernel<<<1, kBlock, 0, s>>>(a, p->v_init);
+        rc = hs(hipGetLastError());
+    }
+    if (rc == CVF_OK && !(p->flags & CVF_KEEP_SIGMA)) {
+        init3_sigma_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        init3_eta_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
+        rc = hs(hipGetLastError());
+    }
+    if (rc == CVF_OK) {                              // initial counters from a recount
+        zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
+        recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        rc = hs(hipGetLastError());
+    }
+    std::vector<int64_t> h((size_t)kRc * kSlots);
+    if (rc == CVF_OK) rc = hs(hipMemcpyAsync(h.data(), a.rc, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (rc == CVF_OK) rc = hs(hipStreamSynchronize(s));
+    if (rc == CVF_OK) {
+        Dev3State ds;
+        rc = hs(hipMemcpy(&ds, a.st, sizeof(ds), hipMemcpyDeviceToHost));
+        if (rc == CVF_OK) {
+            ds.n_hb_raw = ds.n_coop = 0;
+            for (int i = 0; i < kSlots; ++i) {
+                ds.n_hb_raw += h[0 * kSlots + i];
+                ds.n_coop += h[1 * kSlots + i];
+            }
+            rc = hs(hipMemcpy(a.st, &ds, sizeof(ds), hipMemcpyHostToDevice));
+        }
+    }
+    if (rc != CVF_OK) {
+        delete st;
+        return rc;
+    }
+    *out = st;
+    return CVF_OK;
+}
+
+int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
+{
+    if (!st || nsteps < 0) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Lat3 a = st->la;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        t_begin(st, CVF3_K_VOLUME, s);
+        vol3_kernel<<<1, kBlock, 0, s>>>(a, 0);
+        t_end(st, CVF3_K_VOLUME, s);
+        t_begin(st, CVF3_K_ETA, s);
+        eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
+        t_end(st, CVF3_K_ETA, s);
+        for (uint32_t pass = 0; pass < 6; ++pass) {
+            a.pass = pass;
+            t_begin(st, CVF3_K_PASS, s);
+            pass3_kernel<<<blocks_for(a.N / 2), kBlock, 0, s>>>(a);
+            t_end(st, CVF3_K_PASS, s);
+        }
+        const int rc = hs(hipGetLastError());
+        if (rc != CVF_OK) return rc;
+    }
+    return CVF_OK;
+}
+
+int cvf3_observables(cvf3_state* st, cvf3_obs* out, void* stream)
+{
+    if (!st || !out) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Lat3& a = st->la;
+    vol3_kernel<<<1, kBlock, 0, s>>>(a, 1);
+    zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
+    recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+    int rc = hs(hipGetLastError());
+    std::vector<int64_t> h((size_t)kRc * kSlots);
+    Dev3State ds;
+    if (rc == CVF_OK) rc = hs(hipMemcpyAsync(h.data(), a.rc, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (rc == CVF_OK) rc = hs(hipMemcpyAsync(&ds, a.st, sizeof(ds), hipMemcpyDeviceToHost, s));
+    if (rc == CVF_OK) rc = hs(hipStreamSynchronize(s));
+    if (rc != CVF_OK) return rc;
+    int64_t tot[kRc] = {0};
+    for (int k = 0; k < kRc; ++k)
+        for (int i = 0; i < kSlots; ++i) tot[k] += h[(size_t)k * kSlots + i];
+    memset(out, 0, sizeof(*out));
+    const double Nd = a.Nd;
+    out->step = ds.t_next;
+    out->n_hb_raw = tot[0];
+    out->n_hb = ds.theta ? tot[0] : 0;
+    out->n_coop = tot[1];
+    int64_t mx = 0;
+    for (int k = 0; k < 6; ++k) {
+        out->count[k] = tot[2 + k];
+        mx = tot[2 + k] > mx ? tot[2 + k] : mx;
+    }
+    out->n_eta0 = tot[8];
+    out->met_attempted = ds.met_att;
+    out->met_accepted = ds.met_acc;
+    out->eta_attempted = ds.eta_att;
+    out->eta_accepted = ds.eta_acc;
+    out->vol_attempted = ds.vol_att;
+    out->vol_accepted = ds.vol_acc;
+    out->v = ds.v;
+    out->V = (Nd * ds.v) + (st->p.vHB * (double)out->n_hb);
+    out->H = (((Nd * lj3(ds.v, st->htab.r3)) - (st->p.J * (double)out->n_hb)) - (st->p.Jsigma * (double)out->n_coop)) +
+             (st->p.P * out->V);
+    out->M = (double)mx / (6.0 * Nd);
+    out->consistent = (ds.n_hb_raw == tot[0] && ds.n_coop == tot[1]) ? 1 : 0;
+    return CVF_OK;
+}
+
+int cvf3_timing_enable(cvf3_state* st, int enable)
+{
+    if (!st) return CVF_EINVAL;
+    const int rc = drain3(st);
+    for (int k = 0; k < CVF3_K_COUNT; ++k) {
+        st->launches[k] = 0;
+        st->total_ms[k] = 0.0;
+    }
+    st->timing = enable != 0;
+    return rc;
+}
+
+int cvf3_kernel_times(cvf3_state* st, int kind, int64_t* launches, double* mean_ms)
+{
+    if (!st || kind < 0 || kind >= CVF3_K_COUNT || !launches || !mean_ms) return CVF_EINVAL;
+    const int rc = drain3(st);
+    *launches = st->launches[kind];
+    *mean_ms = st->launches[kind] ? st->total_ms[kind] / (double)st->launches[kind] : 0.0;
+    return rc;
+}
+
+int cvf3_destroy(cvf3_state* st)
+{
+    if (!st) return CVF_EINVAL;
+    drain3(st);
+    delete st;
+    return CVF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""GPU parity of the cubic-lattice model with eta (volume move, eta moves over
+the checkerboard cubes, six arm-domain sigma passes per step) against the
+oracle, through the C ABI: sigma, eta and every counter bit for bit after
+each block of steps -- tiny lattices (L = 2 wraps every neighbour), several
+workgroups with ragged tails, liquid, gas and J_eff < 0 state points,
+reduced q, a kept caller state, and the paper's N = 260^3 lattice."""
+import numpy as np
+import pytest
+
+from tests.test_gpu_parity import gpu_params, say
+
+pytestmark = pytest.mark.gpu
+
+INT_KEYS = ("step", "n_hb_raw", "n_hb", "n_coop", "count", "n_eta0", "met_attempted", "met_accepted",
+            "eta_attempted", "eta_accepted", "vol_attempted", "vol_accepted")
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05919_amd import cvf, cvf3
+    cvf.lib()
+    cvf3.lib()
+    return cvf3
+
+
+def compare(ch, oc, ctx):
+    assert np.array_equal(ch.sigma.cpu().numpy(), oc.sigma()), ctx + " sigma"
+    assert np.array_equal(ch.eta.cpu().numpy(), oc.eta()), ctx + " eta"
+    og, oo = ch.obs(), oc.obs()
+    for k in INT_KEYS:
+        assert og[k] == oo[k], (ctx, k, og[k], oo[k])
+    assert og["consistent"] == 1, ctx
+    assert og["v"] == oo["v"], (ctx, og["v"], oo["v"])
+    for k in ("V", "H", "M"):
+        assert og[k] == pytest.approx(oo[k], rel=1e-13, abs=1e-12), (ctx, k)
+    return og
+
+
+def run3(c3, oracle_mod, op, plan, keep=None):
+    from oracle import cvf3 as o3
+    from paper_2505_05919_amd import cvf
+    ctx = f"L={op.L} q={op.q} seed={op.seed} beta={op.beta:.6g} P={op.P:.6g} v0={op.v_init} flags={op.flags}"
+    say("case " + ctx)
+    oc = o3.Chain3(op)
+    if keep is not None:
+        import torch
+        sig, eta = keep
+        oc.set_state(sigma=sig, eta=eta)
+        p = gpu_params(cvf, op)
+        p.flags |= cvf.CVF_KEEP_SIGMA
+        ch = c3.Chain3(p, sigma=torch.from_numpy(sig.copy()).cuda(), eta=torch.from_numpy(eta.copy()).cuda())
+    else:
+        ch = c3.Chain3(gpu_params(cvf, op))
+    compare(ch, oc, ctx + " init")
+    done = 0
+    for n in plan:
+        ch.steps(n)
+        oc.steps(n)
+        done += n
+        og = compare(ch, oc, f"{ctx} after {done}")
+    ch.close()
+    return og
+
+
+@pytest.mark.parametrize("L,plan", [(2, [1, 20]), (4, [1, 10]), (6, [3, 6]), (8, [5]), (10, [4]), (16, [3]),
+                                    (18, [2]), (36, [2]), (64, [1])])
+def test_cvf3_parity(c3, oracle_mod, L, plan):
+    op = oracle_mod.params_from_si(300.0, 0.1, L=L, seed=700 + L)
+    run3(c3, oracle_mod, op, plan)
+
+
+@pytest.mark.parametrize("T,P,v0", [(250.0, 100.0, 1.25), (210.0, 0.1, 1.1), (330.0, 0.1, 2.5), (300.0, 1500.0, 1.2),
+                                    (400.0, -200.0, 1.9)])
+def test_cvf3_state_points(c3, oracle_mod, T, P, v0):
+    """Liquid, cold liquid, gas (eta moves always accepted), J_eff < 0
+    (P v_HB > J), and a volume that crosses v = 2 during the run."""
+    op = oracle_mod.params_from_si(T, P, L=12, seed=int(T) + 3, v_init=v0, dv_max=0.3 if v0 == 1.9 else 0.0125)
+    og = run3(c3, oracle_mod, op, [2, 6])
+    assert og["n_eta0"] == 12 ** 3
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5])
+def test_cvf3_reduced_q(c3, oracle_mod, q):
+    op = oracle_mod.params_from_si(260.0, 25.0, L=14, q=q, seed=800 + q)
+    run3(c3, oracle_mod, op, [4])
+
+
+def test_cvf3_no_volume_move_and_kept_state(c3, oracle_mod):
+    """CVF_KEEP_SIGMA: the chain starts from the caller's sigma and eta (here
+    a state the oracle reached after some steps with another seed)."""
+    from oracle import cvf3 as o3
+    src = o3.Chain3(oracle_mod.params_from_si(280.0, 0.1, L=10, seed=5)).steps(7)
+    keep = (src.sigma(), src.eta())
+    op = oracle_mod.params_from_si(280.0, 0.1, L=10, seed=6, flags=oracle_mod.NO_VOLUME_MOVE)
+    og = run3(c3, oracle_mod, op, [3, 3], keep=keep)
+    assert og["vol_attempted"] == 0
+
+
+def test_cvf3_paper_size(c3, oracle_mod):
+    """N = 260^3 = 17 576 000 (the paper's largest Metropolis lattice): init
+    and one full step bit for bit."""
+    op = oracle_mod.params_from_si(300.0, 0.1, L=260, seed=2026)
+    run3(c3, oracle_mod, op, [1])
