@@ -63,7 +63,7 @@ struct Lat3 {
     uint32_t L, N, h, q;
     uint32_t key0, key1;
     uint32_t pass;
-    uint32_t pad;
+    uint32_t quad;            // 1: L % 4 == 0, four cells per lane; 0: cell pairs
     double   invL, invH, Nd, beta, J, P, vHB, dv_max;
     int32_t  do_volume;
 };
@@ -456,6 +456,65 @@ __device__ __forceinline__ void pass_pair(const Lat3& a, const uint32_t* met, co
         *(uint16_t*)(a.sigma + (size_t)A * N + c0) = (uint16_t)(own0[A] | (own1[A] << 8));
 }
 
+// Four cells per lane (L % 4 == 0): cells 4u..4u+3 of one x-row use the
+// Philox blocks of pairs 2u and 2u+1; own, facing and eta words are 32-bit
+// loads, the x arms' facing and eta words borrow one byte from the next or
+// previous word (wrapping at the row end).
+template <int A>
+__device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, const uint64_t* lim, uint32_t u,
+                                          uint32_t t, int theta, int (&cnt)[3])
+{
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t c0 = 4 * u;
+    uint32_t ow[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) ow[b] = *(const uint32_t*)(a.sigma + (size_t)b * N + c0);
+    uint32_t fw, ew;
+    if (A == 0 || A == 1) {
+        const uint32_t yz = udiv(c0, L, a.invL);
+        const uint32_t x0 = c0 - yz * L;
+        if (A == 0) {                                     // arm 1 of x0+1 .. x0+4
+            const uint32_t nx = x0 + 4 == L ? c0 + 4 - L : c0 + 4;
+            fw = (*(const uint32_t*)(a.sigma + (size_t)N + c0) >> 8) | ((uint32_t)a.sigma[(size_t)N + nx] << 24);
+            ew = *(const uint32_t*)(a.eta + c0);
+        } else {                                          // arm 0 of x0-1 .. x0+2
+            const uint32_t px = x0 == 0 ? c0 + L - 1 : c0 - 1;
+            fw = (*(const uint32_t*)(a.sigma + c0) << 8) | (uint32_t)a.sigma[px];
+            ew = (*(const uint32_t*)(a.eta + c0) << 8) | (uint32_t)a.eta[px];
+        }
+    } else {
+        const uint32_t L2 = L * L;
+        uint32_t o;
+        if (A == 2 || A == 3) {
+            const uint32_t yz = udiv(c0, L, a.invL);
+            const uint32_t z = udiv(yz, L, a.invL);
+            const uint32_t y = yz - z * L;
+            if (A == 2) o = y == L - 1 ? c0 + L - L2 : c0 + L;
+            else o = y == 0 ? c0 + L2 - L : c0 - L;
+        } else if (A == 4) {
+            o = c0 + L2 >= N ? c0 + L2 - N : c0 + L2;
+        } else {
+            o = c0 >= L2 ? c0 - L2 : c0 + N - L2;
+        }
+        fw = *(const uint32_t*)(a.sigma + (size_t)(A ^ 1) * N + o);
+        ew = *(const uint32_t*)(a.eta + (size_t)(A >> 1) * N + ((A & 1) ? o : c0));
+    }
+    const uint4 w0 = philox(2 * u, t, (uint32_t)A, kDom, a.key0, a.key1);
+    const uint4 w1 = philox(2 * u + 1, t, (uint32_t)A, kDom, a.key0, a.key1);
+    const uint32_t prop[4] = {w0.x, w0.z, w1.x, w1.z}, accw[4] = {w0.y, w0.w, w1.y, w1.w};
+    uint32_t out = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t own[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) own[b] = (ow[b] >> (8 * j)) & 0xFFu;
+        move_one(met, lim, (int)a.q, theta, own, A, (fw >> (8 * j)) & 0xFFu, (ew >> (8 * j)) & 0xFFu, prop[j],
+                 accw[j], cnt[0], cnt[1], cnt[2]);
+        out |= own[A] << (8 * j);
+    }
+    if (out != ow[A]) *(uint32_t*)(a.sigma + (size_t)A * N + c0) = out;
+}
+
 __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
 {
     __shared__ uint32_t met[66];
@@ -468,7 +527,18 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
     __syncthreads();
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     int cnt[3] = {0, 0, 0};
-    if (p < a.N / 2) {
+    if (a.quad) {
+        if (p < a.N / 4) {
+            switch (arm) {
+            case 0: pass_quad<0>(a, met, lim, p, t, theta, cnt); break;
+            case 1: pass_quad<1>(a, met, lim, p, t, theta, cnt); break;
+            case 2: pass_quad<2>(a, met, lim, p, t, theta, cnt); break;
+            case 3: pass_quad<3>(a, met, lim, p, t, theta, cnt); break;
+            case 4: pass_quad<4>(a, met, lim, p, t, theta, cnt); break;
+            default: pass_quad<5>(a, met, lim, p, t, theta, cnt); break;
+            }
+        }
+    } else if (p < a.N / 2) {
         switch (arm) {
         case 0: pass_pair<0>(a, met, lim, p, t, theta, cnt); break;
         case 1: pass_pair<1>(a, met, lim, p, t, theta, cnt); break;
@@ -749,6 +819,7 @@ int cvf3_init(const cvf_params* p, uint8_t* d_sigma, uint8_t* d_eta, void* d_wor
     a.vHB = p->vHB;
     a.dv_max = p->dv_max;
     a.do_volume = (p->flags & CVF_NO_VOLUME_MOVE) ? 0 : 1;
+    a.quad = (a.L % 4 == 0) ? 1u : 0u;
     hipStream_t s = (hipStream_t)stream;
     rc = hs(hipMemcpyAsync(st->dtab, &st->htab, sizeof(Tab3), hipMemcpyHostToDevice, s));
     if (rc == CVF_OK) {
@@ -803,7 +874,7 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
         for (uint32_t pass = 0; pass < 6; ++pass) {
             a.pass = pass;
             t_begin(st, CVF3_K_PASS, s);
-            pass3_kernel<<<blocks_for(a.N / 2), kBlock, 0, s>>>(a);
+            pass3_kernel<<<blocks_for(a.quad ? a.N / 4 : a.N / 2), kBlock, 0, s>>>(a);
             t_end(st, CVF3_K_PASS, s);
         }
         const int rc = hs(hipGetLastError());
