@@ -64,7 +64,7 @@ struct Lat3 {
     uint32_t key0, key1;
     uint32_t pass;
     uint32_t quad;            // 1: L % 4 == 0, four cells per lane; 0: cell pairs
-    double   invL, invH, Nd, beta, J, P, vHB, dv_max;
+    double   invL, invH, invQ4, Nd, beta, J, P, vHB, dv_max;
     int32_t  do_volume;
 };
 
@@ -361,6 +361,129 @@ __global__ __launch_bounds__(kBlock) void eta3_kernel(Lat3 a)
         const int slot = threadIdx.x == 0 ? 0 : 3;
         if (s) atomicAdd((unsigned long long*)(a.slots + (size_t)slot * kSlots + blockIdx.x % kSlots),
                          (unsigned long long)s);
+    }
+}
+
+// Two cubes per lane (L % 4 == 0): cubes 2i', 2i'+1 of one parity and one
+// (j, l) span x = 4i' + par .. 4i' + par + 3, so every plane row the pair
+// touches is one aligned 32-bit word (plus, for the odd parity, the first
+// byte of the next word, wrapping at the row end): 24 row loads for 24
+// edges.  Each cube's move is the one of eta3_kernel.
+__device__ __forceinline__ uint64_t row5(const uint8_t* plane, uint32_t rowbase, uint32_t xa, uint32_t xb, bool odd)
+{
+    uint64_t w = *(const uint32_t*)(plane + rowbase + xa);
+    if (odd) w |= (uint64_t)plane[rowbase + xb] << 32;
+    return w;
+}
+
+__device__ __forceinline__ uint32_t byte_at(uint64_t w, uint32_t i) { return (uint32_t)(w >> (8 * i)) & 0xFFu; }
+
+__global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
+{
+    const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t npar = a.N / 16;
+    int cnt[2] = {0, 0};
+    if (g < 2 * npar) {
+        const uint32_t L = a.L, N = a.N, h = a.h;
+        const uint32_t par = g >= npar ? 1u : 0u;
+        const bool odd = par != 0;
+        const uint32_t r = g - par * npar;
+        const uint32_t q4 = L / 4;
+        const uint32_t jl = udiv(r, q4, a.invQ4);
+        const uint32_t ip = r - jl * q4;
+        const uint32_t l = udiv(jl, h, a.invH);
+        const uint32_t j = jl - l * h;
+        const uint32_t yv[2] = {2 * j + par, 2 * j + par + 1 == L ? 0u : 2 * j + par + 1};
+        const uint32_t zv[2] = {2 * l + par, 2 * l + par + 1 == L ? 0u : 2 * l + par + 1};
+        const uint32_t xa = 4 * ip, xb = xa + 4 == L ? 0u : xa + 4;
+        uint32_t rb[2][2];                                 // [dy][dz] row bases
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz) rb[dy][dz] = L * (yv[dy] + L * zv[dz]);
+        const uint8_t* S = a.sigma;
+        const uint8_t* E = a.eta;
+        uint64_t e0[2][2], s0[2][2], s1[2][2], e1[2], s2[2], s3[2], e2[2], s4[2], s5[2];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz) {
+                e0[dy][dz] = row5(E, rb[dy][dz], xa, xb, odd);
+                s0[dy][dz] = row5(S, rb[dy][dz], xa, xb, odd);
+                s1[dy][dz] = row5(S + (size_t)N, rb[dy][dz], xa, xb, odd);
+            }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            e1[k] = row5(E + (size_t)N, rb[0][k], xa, xb, odd);          // y-edges: row (y0, z_k)
+            s2[k] = row5(S + 2 * (size_t)N, rb[0][k], xa, xb, odd);
+            s3[k] = row5(S + 3 * (size_t)N, rb[1][k], xa, xb, odd);      // upper ends: row (y1, z_k)
+            e2[k] = row5(E + 2 * (size_t)N, rb[k][0], xa, xb, odd);      // z-edges: row (y_k, z0)
+            s4[k] = row5(S + 4 * (size_t)N, rb[k][0], xa, xb, odd);
+            s5[k] = row5(S + 5 * (size_t)N, rb[k][1], xa, xb, odd);      // upper ends: row (y_k, z1)
+        }
+        const uint32_t t = (uint32_t)a.st->t_cur;
+        const int theta = a.st->theta;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t k = par * (h * h * h) + 2 * ip + (uint32_t)c + h * jl;
+            const uint4 w = philox(k, t, 0u, kEta, a.key0, a.key1);
+            const int m = pick_div(w.x, 9);
+            if (m < 0) continue;
+            const uint32_t mask = a.tab->match[m];
+            const uint32_t b0 = par + 2 * c;               // byte of the cube's lowest x in the row words
+            uint32_t old = 0, eqm = 0;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int lo = rr & 1, hi = rr >> 1;
+                // x-edge (dy, dz) = (lo, hi)
+                old |= byte_at(e0[lo][hi], b0) << rr;
+                eqm |= (uint32_t)(byte_at(s0[lo][hi], b0) == byte_at(s1[lo][hi], b0 + 1)) << rr;
+                // y-edge (dx, dz) = (lo, hi)
+                old |= byte_at(e1[hi], b0 + lo) << (4 + rr);
+                eqm |= (uint32_t)(byte_at(s2[hi], b0 + lo) == byte_at(s3[hi], b0 + lo)) << (4 + rr);
+                // z-edge (dx, dy) = (lo, hi)
+                old |= byte_at(e2[hi], b0 + lo) << (8 + rr);
+                eqm |= (uint32_t)(byte_at(s4[hi], b0 + lo) == byte_at(s5[hi], b0 + lo)) << (8 + rr);
+            }
+            const uint32_t neu = (~mask) & 0xFFFu;
+            const int dn = __popc(neu & eqm) - __popc(old & eqm);
+            bool acc = true;
+            if (theta) {
+                const uint32_t thr = a.tab->eta[dn + 4];
+                acc = thr == 0xFFFFFFFFu || w.y < thr;
+            }
+            if (!acc) continue;
+            cnt[0] += dn;
+            cnt[1] += 1;
+            const uint32_t chg = neu ^ old;
+            if (!chg) continue;
+#pragma unroll
+            for (int e = 0; e < 12; ++e) {
+                if (!((chg >> e) & 1)) continue;
+                const int d = e >> 2, lo = e & 1, hi = (e >> 1) & 1;
+                uint32_t rbase, bx;
+                if (d == 0) { rbase = rb[lo][hi]; bx = b0; }
+                else if (d == 1) { rbase = rb[0][hi]; bx = b0 + lo; }
+                else { rbase = rb[hi][0]; bx = b0 + lo; }
+                const uint32_t x = bx == 4 ? xb : xa + bx;
+                a.eta[(size_t)d * N + rbase + x] = (uint8_t)((neu >> e) & 1);
+            }
+        }
+    }
+    __shared__ int part[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int sm = wave_sum(cnt[q]);
+        if (lane == 0) part[q][wv] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int64_t sm = 0;
+        for (int i = 0; i < kBlock / 64; ++i) sm += part[threadIdx.x][i];
+        const int slot = threadIdx.x == 0 ? 0 : 3;
+        if (sm) atomicAdd((unsigned long long*)(a.slots + (size_t)slot * kSlots + blockIdx.x % kSlots),
+                          (unsigned long long)sm);
     }
 }
 
@@ -812,6 +935,7 @@ int cvf3_init(const cvf_params* p, uint8_t* d_sigma, uint8_t* d_eta, void* d_wor
     a.key1 = (uint32_t)(p->seed >> 32);
     a.invL = 1.0 / (double)a.L;
     a.invH = 1.0 / (double)a.h;
+    a.invQ4 = 1.0 / (double)(a.L / 4 ? a.L / 4 : 1);
     a.Nd = (double)a.N;
     a.beta = p->beta;
     a.J = p->J;
@@ -869,7 +993,8 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
         vol3_kernel<<<1, kBlock, 0, s>>>(a, 0);
         t_end(st, CVF3_K_VOLUME, s);
         t_begin(st, CVF3_K_ETA, s);
-        eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
+        if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
+        else eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
         t_end(st, CVF3_K_ETA, s);
         for (uint32_t pass = 0; pass < 6; ++pass) {
             a.pass = pass;
