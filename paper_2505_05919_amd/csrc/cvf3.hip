@@ -49,7 +49,6 @@ struct Tab3 {
     uint32_t met[2][3][11];   // sigma move: [theta*eta][dh+1][dc+5]
     uint32_t eta[9];          // eta move in the liquid: [dn+4]
     uint32_t match[9];        // perfect matchings of the cube graph (12-bit edge masks, eta = 0)
-    uint64_t lim[6];          // lim[i] = i floor(2^32/(q-1)), i = 1..q-1 (uniform pick over q-1)
     double   r3[40];          // r3(m), m = 0..36
 };
 
@@ -126,6 +125,17 @@ __device__ __forceinline__ int pick_div(uint32_t w, uint32_t k)
     const uint32_t d = (uint32_t)(4294967296ull / k);
     if ((uint64_t)w >= (uint64_t)k * d) return -1;
     return (int)(w / d);
+}
+
+// The exact-block draw of {0..q-2} from one word, in closed form: with
+// d = floor(2^32/(q-1)), (q-1) d = 2^32 when q-1 is a power of two (never
+// NONE, k = floor(w (q-1) / 2^32)) and 2^32 - 1 when q-1 is 3 or 5 (NONE only
+// for w = 2^32 - 1, k = floor((w+1)(q-1) / 2^32)).  Returns false for NONE.
+__device__ __forceinline__ bool pick_other(uint32_t w, uint32_t qm1, bool odd, uint32_t& k)
+{
+    if (odd && w == 0xFFFFFFFFu) return false;
+    k = __umulhi(odd ? w + 1 : w, qm1);
+    return true;
 }
 
 // Corner vtx (bit 0: +x, 1: +y, 2: +z) of cube k: parity k / h^3 sets the
@@ -494,14 +504,13 @@ __global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
 // pairs are 16-bit loads; the x arms' facing and eta pairs straddle the pair
 // and wrap at the row end, so they are byte loads.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void move_one(const uint32_t* met, const uint64_t* lim, int q, int theta, uint32_t own[6],
+__device__ __forceinline__ void move_one(const uint32_t* met, int q, int theta, uint32_t own[6],
                                          int A, uint32_t facing, uint32_t eta, uint32_t prop, uint32_t accw,
                                          int& dhb, int& dco, int& nacc)
 {
-    if ((uint64_t)prop >= lim[q - 1]) return;            // NONE
-    int k = 0;
-#pragma unroll
-    for (int i = 1; i < 5; ++i) k += (i < q - 1 && (uint64_t)prop >= lim[i]) ? 1 : 0;
+    const uint32_t qm1 = (uint32_t)q - 1;
+    uint32_t k;
+    if (!pick_other(prop, qm1, (qm1 & 1) && qm1 > 1, k)) return;      // NONE
     const uint32_t old = own[A];
     uint32_t neu = old + 1 + (uint32_t)k;
     neu = neu >= (uint32_t)q ? neu - (uint32_t)q : neu;
@@ -521,7 +530,7 @@ __device__ __forceinline__ void move_one(const uint32_t* met, const uint64_t* li
 }
 
 template <int A>
-__device__ __forceinline__ void pass_pair(const Lat3& a, const uint32_t* met, const uint64_t* lim, uint32_t p,
+__device__ __forceinline__ void pass_pair(const Lat3& a, const uint32_t* met, uint32_t p,
                                           uint32_t t, int theta, int (&cnt)[3])
 {
     const uint32_t L = a.L, N = a.N;
@@ -573,18 +582,29 @@ __device__ __forceinline__ void pass_pair(const Lat3& a, const uint32_t* met, co
     }
     const uint4 w = philox(p, t, (uint32_t)A, kDom, a.key0, a.key1);
     const uint32_t old0 = own0[A], old1 = own1[A];
-    move_one(met, lim, (int)a.q, theta, own0, A, f0, e0, w.x, w.y, cnt[0], cnt[1], cnt[2]);
-    move_one(met, lim, (int)a.q, theta, own1, A, f1, e1, w.z, w.w, cnt[0], cnt[1], cnt[2]);
+    move_one(met, (int)a.q, theta, own0, A, f0, e0, w.x, w.y, cnt[0], cnt[1], cnt[2]);
+    move_one(met, (int)a.q, theta, own1, A, f1, e1, w.z, w.w, cnt[0], cnt[1], cnt[2]);
     if (own0[A] != old0 || own1[A] != old1)
         *(uint16_t*)(a.sigma + (size_t)A * N + c0) = (uint16_t)(own0[A] | (own1[A] << 8));
 }
 
+// 0x01 in every byte of x that is zero, 0x00 elsewhere (no carry crosses a byte).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t x)
+{
+    return (~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu)) >> 7;
+}
+
+// Sum of the four bytes of x (each small enough that no partial sum reaches 256).
+__device__ __forceinline__ uint32_t byte_sum(uint32_t x) { return (x * 0x01010101u) >> 24; }
+
 // Four cells per lane (L % 4 == 0): cells 4u..4u+3 of one x-row use the
 // Philox blocks of pairs 2u and 2u+1; own, facing and eta words are 32-bit
 // loads, the x arms' facing and eta words borrow one byte from the next or
-// previous word (wrapping at the row end).
+// previous word (wrapping at the row end).  The four moves are decided
+// together on packed bytes: the same proposals, table index and acceptance
+// as move_one, cell by cell.
 template <int A>
-__device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, const uint64_t* lim, uint32_t u,
+__device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, uint32_t u,
                                           uint32_t t, int theta, int (&cnt)[3])
 {
     const uint32_t L = a.L, N = a.N;
@@ -625,25 +645,55 @@ __device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, co
     const uint4 w0 = philox(2 * u, t, (uint32_t)A, kDom, a.key0, a.key1);
     const uint4 w1 = philox(2 * u + 1, t, (uint32_t)A, kDom, a.key0, a.key1);
     const uint32_t prop[4] = {w0.x, w0.z, w1.x, w1.z}, accw[4] = {w0.y, w0.w, w1.y, w1.w};
-    uint32_t out = 0;
+    // proposals of the four cells, one byte each (a NONE draw keeps the old state)
+    const uint32_t q = a.q, qm1 = q - 1, oldw = ow[A];
+    const bool odd = (qm1 & 1) && qm1 > 1;
+    uint32_t nw = 0, valid = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        uint32_t own[6];
-#pragma unroll
-        for (int b = 0; b < 6; ++b) own[b] = (ow[b] >> (8 * j)) & 0xFFu;
-        move_one(met, lim, (int)a.q, theta, own, A, (fw >> (8 * j)) & 0xFFu, (ew >> (8 * j)) & 0xFFu, prop[j],
-                 accw[j], cnt[0], cnt[1], cnt[2]);
-        out |= own[A] << (8 * j);
+        const uint32_t old = (oldw >> (8 * j)) & 0xFFu;
+        uint32_t k = 0;
+        const bool ok = pick_other(prop[j], qm1, odd, k);
+        uint32_t neu = old + 1 + k;
+        neu = neu >= q ? neu - q : neu;
+        neu = ok ? neu : old;
+        valid |= ok ? (0xFFu << (8 * j)) : 0u;
+        nw |= neu << (8 * j);
     }
-    if (out != ow[A]) *(uint32_t*)(a.sigma + (size_t)A * N + c0) = out;
+    // equal-byte counts for all four cells at once: cn / co = other arms equal
+    // to the new / old state, hn / ho = facing arm equal to the new / old state
+    uint32_t cn = 0, co = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        if (b == A) continue;
+        cn += zero_bytes(nw ^ ow[b]);
+        co += zero_bytes(oldw ^ ow[b]);
+    }
+    const uint32_t hn = zero_bytes(nw ^ fw), ho = zero_bytes(oldw ^ fw);
+    const uint32_t thw = theta ? (ew & 0x01010101u) : 0u;
+    // table index th*33 + (dh+1)*11 + dc+5 per byte; every byte of the first
+    // term is >= 16 >= every byte of the second, so no borrow crosses bytes
+    const uint32_t idxw = (11u * hn + cn + 0x10101010u + 33u * thw) - (11u * ho + co);
+    uint32_t accm = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t thr = met[(idxw >> (8 * j)) & 0xFFu];
+        const bool acc = thr == 0xFFFFFFFFu || accw[j] < thr;
+        accm |= acc ? (0xFFu << (8 * j)) : 0u;
+    }
+    accm &= valid;
+    const uint32_t out = (nw & accm) | (oldw & ~accm);
+    const uint32_t em = accm & (ew * 0xFFu);            // accepted cells whose edge has eta = 1
+    cnt[0] += (int)byte_sum(hn & em) - (int)byte_sum(ho & em);
+    cnt[1] += (int)byte_sum(cn & accm) - (int)byte_sum(co & accm);
+    cnt[2] += __popc(accm) >> 3;
+    if (out != oldw) *(uint32_t*)(a.sigma + (size_t)A * N + c0) = out;
 }
 
 __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
 {
     __shared__ uint32_t met[66];
-    __shared__ uint64_t lim[6];
     if (threadIdx.x < 66) met[threadIdx.x] = (&a.tab->met[0][0][0])[threadIdx.x];
-    if (threadIdx.x < 6) lim[threadIdx.x] = a.tab->lim[threadIdx.x];
     const int arm = a.st->order[a.pass];
     const uint32_t t = (uint32_t)a.st->t_cur;
     const int theta = a.st->theta;
@@ -653,22 +703,22 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
     if (a.quad) {
         if (p < a.N / 4) {
             switch (arm) {
-            case 0: pass_quad<0>(a, met, lim, p, t, theta, cnt); break;
-            case 1: pass_quad<1>(a, met, lim, p, t, theta, cnt); break;
-            case 2: pass_quad<2>(a, met, lim, p, t, theta, cnt); break;
-            case 3: pass_quad<3>(a, met, lim, p, t, theta, cnt); break;
-            case 4: pass_quad<4>(a, met, lim, p, t, theta, cnt); break;
-            default: pass_quad<5>(a, met, lim, p, t, theta, cnt); break;
+            case 0: pass_quad<0>(a, met, p, t, theta, cnt); break;
+            case 1: pass_quad<1>(a, met, p, t, theta, cnt); break;
+            case 2: pass_quad<2>(a, met, p, t, theta, cnt); break;
+            case 3: pass_quad<3>(a, met, p, t, theta, cnt); break;
+            case 4: pass_quad<4>(a, met, p, t, theta, cnt); break;
+            default: pass_quad<5>(a, met, p, t, theta, cnt); break;
             }
         }
     } else if (p < a.N / 2) {
         switch (arm) {
-        case 0: pass_pair<0>(a, met, lim, p, t, theta, cnt); break;
-        case 1: pass_pair<1>(a, met, lim, p, t, theta, cnt); break;
-        case 2: pass_pair<2>(a, met, lim, p, t, theta, cnt); break;
-        case 3: pass_pair<3>(a, met, lim, p, t, theta, cnt); break;
-        case 4: pass_pair<4>(a, met, lim, p, t, theta, cnt); break;
-        default: pass_pair<5>(a, met, lim, p, t, theta, cnt); break;
+        case 0: pass_pair<0>(a, met, p, t, theta, cnt); break;
+        case 1: pass_pair<1>(a, met, p, t, theta, cnt); break;
+        case 2: pass_pair<2>(a, met, p, t, theta, cnt); break;
+        case 3: pass_pair<3>(a, met, p, t, theta, cnt); break;
+        case 4: pass_pair<4>(a, met, p, t, theta, cnt); break;
+        default: pass_pair<5>(a, met, p, t, theta, cnt); break;
         }
     }
     block_slots<3>(cnt, a.slots);                     // slots 0, 1, 2
@@ -813,8 +863,6 @@ void build_tab3(const cvf_params* p, Tab3* t)
                 t->met[th][dh + 1][dc + 5] = thr_of(p->beta, -((double)th * Jeff * (double)dh) - p->Jsigma * (double)dc);
     for (int dn = -4; dn <= 4; ++dn) t->eta[dn + 4] = thr_of(p->beta, -(Jeff * (double)dn));
     cube_matchings(t->match);
-    const uint64_t d = 4294967296ull / (uint64_t)(p->q - 1);
-    for (int i = 0; i < 6; ++i) t->lim[i] = (uint64_t)i * d;
     for (int m = 0; m < 40; ++m) t->r3[m] = m <= 36 ? sphere_points(m) : 0.0;
 }
 

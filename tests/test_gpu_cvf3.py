@@ -82,9 +82,12 @@ def test_cvf3_state_points(c3, oracle_mod, T, P, v0):
     assert og["n_eta0"] == 12 ** 3
 
 
+@pytest.mark.parametrize("L", [14, 16])
 @pytest.mark.parametrize("q", [2, 3, 4, 5])
-def test_cvf3_reduced_q(c3, oracle_mod, q):
-    op = oracle_mod.params_from_si(260.0, 25.0, L=14, q=q, seed=800 + q)
+def test_cvf3_reduced_q(c3, oracle_mod, q, L):
+    """q - 1 = 1, 2, 4 (power-of-two draws, never NONE) and 3 (NONE at the
+    top word), on the pair path (L = 14) and the quad path (L = 16)."""
+    op = oracle_mod.params_from_si(260.0, 25.0, L=L, q=q, seed=800 + q)
     run3(c3, oracle_mod, op, [4])
 
 
