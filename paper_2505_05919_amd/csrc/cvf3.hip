@@ -375,18 +375,20 @@ __global__ __launch_bounds__(kBlock) void eta3_kernel(Lat3 a)
 }
 
 // Two cubes per lane (L % 4 == 0): cubes 2i', 2i'+1 of one parity and one
-// (j, l) span x = 4i' + par .. 4i' + par + 3, so every plane row the pair
-// touches is one aligned 32-bit word (plus, for the odd parity, the first
-// byte of the next word, wrapping at the row end): 24 row loads for 24
-// edges.  Each cube's move is the one of eta3_kernel.
-__device__ __forceinline__ uint64_t row5(const uint8_t* plane, uint32_t rowbase, uint32_t xa, uint32_t xb, bool odd)
+// (j, l) span x = 4i' + par .. 4i' + par + 3.  Every plane row the pair
+// touches is one aligned 32-bit word for the even parity; for the odd parity
+// the word is shifted down one byte and takes the first byte of the next
+// word (wrapping at the row end), so that byte i of a row word is always
+// x = 4i' + par + i: 24 row words for 24 edges.  Each cube's move is the one
+// of eta3_kernel.
+__device__ __forceinline__ uint32_t row4(const uint8_t* plane, uint32_t rowbase, uint32_t xa, uint32_t xb, bool odd)
 {
-    uint64_t w = *(const uint32_t*)(plane + rowbase + xa);
-    if (odd) w |= (uint64_t)plane[rowbase + xb] << 32;
-    return w;
+    const uint32_t w = *(const uint32_t*)(plane + rowbase + xa);
+    if (!odd) return w;
+    return __builtin_amdgcn_alignbyte((uint32_t)plane[rowbase + xb], w, 1);
 }
 
-__device__ __forceinline__ uint32_t byte_at(uint64_t w, uint32_t i) { return (uint32_t)(w >> (8 * i)) & 0xFFu; }
+__device__ __forceinline__ uint32_t byte_at(uint32_t w, uint32_t i) { return (w >> (8 * i)) & 0xFFu; }
 
 __global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
 {
@@ -413,23 +415,23 @@ __global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
             for (int dz = 0; dz < 2; ++dz) rb[dy][dz] = L * (yv[dy] + L * zv[dz]);
         const uint8_t* S = a.sigma;
         const uint8_t* E = a.eta;
-        uint64_t e0[2][2], s0[2][2], s1[2][2], e1[2], s2[2], s3[2], e2[2], s4[2], s5[2];
+        uint32_t e0[2][2], s0[2][2], s1[2][2], e1[2], s2[2], s3[2], e2[2], s4[2], s5[2];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
             for (int dz = 0; dz < 2; ++dz) {
-                e0[dy][dz] = row5(E, rb[dy][dz], xa, xb, odd);
-                s0[dy][dz] = row5(S, rb[dy][dz], xa, xb, odd);
-                s1[dy][dz] = row5(S + (size_t)N, rb[dy][dz], xa, xb, odd);
+                e0[dy][dz] = row4(E, rb[dy][dz], xa, xb, odd);
+                s0[dy][dz] = row4(S, rb[dy][dz], xa, xb, odd);
+                s1[dy][dz] = row4(S + (size_t)N, rb[dy][dz], xa, xb, odd);
             }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            e1[k] = row5(E + (size_t)N, rb[0][k], xa, xb, odd);          // y-edges: row (y0, z_k)
-            s2[k] = row5(S + 2 * (size_t)N, rb[0][k], xa, xb, odd);
-            s3[k] = row5(S + 3 * (size_t)N, rb[1][k], xa, xb, odd);      // upper ends: row (y1, z_k)
-            e2[k] = row5(E + 2 * (size_t)N, rb[k][0], xa, xb, odd);      // z-edges: row (y_k, z0)
-            s4[k] = row5(S + 4 * (size_t)N, rb[k][0], xa, xb, odd);
-            s5[k] = row5(S + 5 * (size_t)N, rb[k][1], xa, xb, odd);      // upper ends: row (y_k, z1)
+            e1[k] = row4(E + (size_t)N, rb[0][k], xa, xb, odd);          // y-edges: row (y0, z_k)
+            s2[k] = row4(S + 2 * (size_t)N, rb[0][k], xa, xb, odd);
+            s3[k] = row4(S + 3 * (size_t)N, rb[1][k], xa, xb, odd);      // upper ends: row (y1, z_k)
+            e2[k] = row4(E + 2 * (size_t)N, rb[k][0], xa, xb, odd);      // z-edges: row (y_k, z0)
+            s4[k] = row4(S + 4 * (size_t)N, rb[k][0], xa, xb, odd);
+            s5[k] = row4(S + 5 * (size_t)N, rb[k][1], xa, xb, odd);      // upper ends: row (y_k, z1)
         }
         const uint32_t t = (uint32_t)a.st->t_cur;
         const int theta = a.st->theta;
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
             const int m = pick_div(w.x, 9);
             if (m < 0) continue;
             const uint32_t mask = a.tab->match[m];
-            const uint32_t b0 = par + 2 * c;               // byte of the cube's lowest x in the row words
+            const uint32_t b0 = 2 * c;                     // byte of the cube's lowest x in the row words
             uint32_t old = 0, eqm = 0;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void eta3_pair_kernel(Lat3 a)
                 if (d == 0) { rbase = rb[lo][hi]; bx = b0; }
                 else if (d == 1) { rbase = rb[0][hi]; bx = b0 + lo; }
                 else { rbase = rb[hi][0]; bx = b0 + lo; }
-                const uint32_t x = bx == 4 ? xb : xa + bx;
+                const uint32_t x = par + bx == 4 ? xb : xa + par + bx;
                 a.eta[(size_t)d * N + rbase + x] = (uint8_t)((neu >> e) & 1);
             }
         }
