@@ -723,7 +723,25 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
         default: pass_pair<5>(a, met, p, t, theta, cnt); break;
         }
     }
-    block_slots<3>(cnt, a.slots);                     // slots 0, 1, 2
+    // The three counters of a lane (d N_HB_raw in [-4, 4], d N_sigma in
+    // [-20, 20], accepted in [0, 4]) biased and packed into one word, so one
+    // wave sum serves all three: 64-lane sums stay below 2^10, 2^12 and 2^9.
+    const uint32_t packed = (uint32_t)(cnt[1] + 20) | ((uint32_t)(cnt[0] + 4) << 12) | ((uint32_t)cnt[2] << 22);
+    const uint32_t ws = (uint32_t)wave_sum((int)packed);
+    __shared__ int part[3][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[1][wv] = (int)(ws & 0xFFFu) - 64 * 20;
+        part[0][wv] = (int)((ws >> 12) & 0x3FFu) - 64 * 4;
+        part[2][wv] = (int)(ws >> 22);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int64_t sm = 0;
+        for (int i = 0; i < kBlock / 64; ++i) sm += part[threadIdx.x][i];
+        if (sm) atomicAdd((unsigned long long*)(a.slots + (size_t)threadIdx.x * kSlots + blockIdx.x % kSlots),
+                          (unsigned long long)sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
