@@ -34,6 +34,7 @@ constexpr int kSlots = 256;              // counter slots, spread to avoid one h
 constexpr int kAcc = 4;                  // d N_HB_raw, d N_sigma, sigma accepted, eta accepted
 constexpr int kRc = 10;                  // recount: N_HB_raw, N_sigma, N_q' (6), eta = 0 edges, spare
 constexpr int kBlock = 256;
+constexpr uint32_t kQuadsPerLane = 2;    // quad pass: quads per lane (grid-stride)
 
 struct Dev3State {
     double  v, u;
@@ -703,16 +704,19 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     int cnt[3] = {0, 0, 0};
     if (a.quad) {
-        if (p < a.N / 4) {
-            switch (arm) {
-            case 0: pass_quad<0>(a, met, p, t, theta, cnt); break;
-            case 1: pass_quad<1>(a, met, p, t, theta, cnt); break;
-            case 2: pass_quad<2>(a, met, p, t, theta, cnt); break;
-            case 3: pass_quad<3>(a, met, p, t, theta, cnt); break;
-            case 4: pass_quad<4>(a, met, p, t, theta, cnt); break;
-            default: pass_quad<5>(a, met, p, t, theta, cnt); break;
-            }
+        // grid-stride over the quads: kQuadsPerLane per lane spreads the
+        // lane's fixed work (table load, counter reduction) over more moves
+        const uint32_t nq = a.N / 4, stride = gridDim.x * kBlock;
+#define CVF3_QUADS(ARM) for (uint32_t u = p; u < nq; u += stride) pass_quad<ARM>(a, met, u, t, theta, cnt)
+        switch (arm) {
+        case 0: CVF3_QUADS(0); break;
+        case 1: CVF3_QUADS(1); break;
+        case 2: CVF3_QUADS(2); break;
+        case 3: CVF3_QUADS(3); break;
+        case 4: CVF3_QUADS(4); break;
+        default: CVF3_QUADS(5); break;
         }
+#undef CVF3_QUADS
     } else if (p < a.N / 2) {
         switch (arm) {
         case 0: pass_pair<0>(a, met, p, t, theta, cnt); break;
@@ -723,17 +727,26 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
         default: pass_pair<5>(a, met, p, t, theta, cnt); break;
         }
     }
-    // The three counters of a lane (d N_HB_raw in [-4, 4], d N_sigma in
-    // [-20, 20], accepted in [0, 4]) biased and packed into one word, so one
-    // wave sum serves all three: 64-lane sums stay below 2^10, 2^12 and 2^9.
-    const uint32_t packed = (uint32_t)(cnt[1] + 20) | ((uint32_t)(cnt[0] + 4) << 12) | ((uint32_t)cnt[2] << 22);
-    const uint32_t ws = (uint32_t)wave_sum((int)packed);
+    // The three counters of a lane (d N_HB_raw in [-8, 8], d N_sigma in
+    // [-40, 40], accepted in [0, 8] for two quads) biased and packed into one
+    // word and summed over 16 lanes (sums below 2^9, 2^11, 2^8), then
+    // unpacked and summed over the four 16-lane rows.
+    static_assert(kQuadsPerLane == 2, "field widths below hold for two quads per lane");
+    uint32_t v = (uint32_t)(cnt[1] + 40) | ((uint32_t)(cnt[0] + 8) << 11) | ((uint32_t)cnt[2] << 20);
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    int r3[3] = {(int)((v >> 11) & 0x1FFu) - 16 * 8, (int)(v & 0x7FFu) - 16 * 40, (int)(v >> 20)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r3[k] += __shfl_xor(r3[k], 16, 64);
+        r3[k] += __shfl_xor(r3[k], 32, 64);
+    }
     __shared__ int part[3][kBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
-        part[1][wv] = (int)(ws & 0xFFFu) - 64 * 20;
-        part[0][wv] = (int)((ws >> 12) & 0x3FFu) - 64 * 4;
-        part[2][wv] = (int)(ws >> 22);
+        part[0][wv] = r3[0];
+        part[1][wv] = r3[1];
+        part[2][wv] = r3[2];
     }
     __syncthreads();
     if (threadIdx.x < 3) {
@@ -1067,7 +1080,8 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
         for (uint32_t pass = 0; pass < 6; ++pass) {
             a.pass = pass;
             t_begin(st, CVF3_K_PASS, s);
-            pass3_kernel<<<blocks_for(a.quad ? a.N / 4 : a.N / 2), kBlock, 0, s>>>(a);
+            pass3_kernel<<<blocks_for(a.quad ? (a.N / 4 + kQuadsPerLane - 1) / kQuadsPerLane : a.N / 2), kBlock, 0,
+                           s>>>(a);
             t_end(st, CVF3_K_PASS, s);
         }
         const int rc = hs(hipGetLastError());
