@@ -606,27 +606,46 @@ __device__ __forceinline__ uint32_t byte_sum(uint32_t x) { return (x * 0x0101010
 // previous word (wrapping at the row end).  The four moves are decided
 // together on packed bytes: the same proposals, table index and acceptance
 // as move_one, cell by cell.
+// Raw buffer over one plane (N bytes < 2^31): 32-bit lane offsets, base in SGPRs.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(uint8_t* base, uint32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)n, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t bld32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t bld8(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+
 template <int A>
-__device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, uint32_t u,
-                                          uint32_t t, int theta, int (&cnt)[3])
+__device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, uint32_t u, uint32_t t, int theta,
+                                          int (&cnt)[3])
 {
     const uint32_t L = a.L, N = a.N;
     const uint32_t c0 = 4 * u;
     uint32_t ow[6];
 #pragma unroll
-    for (int b = 0; b < 6; ++b) ow[b] = *(const uint32_t*)(a.sigma + (size_t)b * N + c0);
+    for (int b = 0; b < 6; ++b) ow[b] = bld32(plane_rsrc(a.sigma + (size_t)b * N, N), c0);
     uint32_t fw, ew;
     if (A == 0 || A == 1) {
         const uint32_t yz = udiv(c0, L, a.invL);
         const uint32_t x0 = c0 - yz * L;
+        const __amdgpu_buffer_rsrc_t e0 = plane_rsrc(a.eta, N);
         if (A == 0) {                                     // arm 1 of x0+1 .. x0+4
             const uint32_t nx = x0 + 4 == L ? c0 + 4 - L : c0 + 4;
-            fw = (*(const uint32_t*)(a.sigma + (size_t)N + c0) >> 8) | ((uint32_t)a.sigma[(size_t)N + nx] << 24);
-            ew = *(const uint32_t*)(a.eta + c0);
+            const __amdgpu_buffer_rsrc_t s1 = plane_rsrc(a.sigma + (size_t)N, N);
+            fw = __builtin_amdgcn_alignbyte(bld8(s1, nx), ow[1], 1);
+            ew = bld32(e0, c0);
         } else {                                          // arm 0 of x0-1 .. x0+2
             const uint32_t px = x0 == 0 ? c0 + L - 1 : c0 - 1;
-            fw = (*(const uint32_t*)(a.sigma + c0) << 8) | (uint32_t)a.sigma[px];
-            ew = (*(const uint32_t*)(a.eta + c0) << 8) | (uint32_t)a.eta[px];
+            const __amdgpu_buffer_rsrc_t s0 = plane_rsrc(a.sigma, N);
+            fw = (ow[0] << 8) | bld8(s0, px);
+            ew = (bld32(e0, c0) << 8) | bld8(e0, px);
         }
     } else {
         const uint32_t L2 = L * L;
@@ -642,8 +661,8 @@ __device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, ui
         } else {
             o = c0 >= L2 ? c0 - L2 : c0 + N - L2;
         }
-        fw = *(const uint32_t*)(a.sigma + (size_t)(A ^ 1) * N + o);
-        ew = *(const uint32_t*)(a.eta + (size_t)(A >> 1) * N + ((A & 1) ? o : c0));
+        fw = bld32(plane_rsrc(a.sigma + (size_t)(A ^ 1) * N, N), o);
+        ew = bld32(plane_rsrc(a.eta + (size_t)(A >> 1) * N, N), (A & 1) ? o : c0);
     }
     const uint4 w0 = philox(2 * u, t, (uint32_t)A, kDom, a.key0, a.key1);
     const uint4 w1 = philox(2 * u + 1, t, (uint32_t)A, kDom, a.key0, a.key1);
@@ -690,7 +709,7 @@ __device__ __forceinline__ void pass_quad(const Lat3& a, const uint32_t* met, ui
     cnt[0] += (int)byte_sum(hn & em) - (int)byte_sum(ho & em);
     cnt[1] += (int)byte_sum(cn & accm) - (int)byte_sum(co & accm);
     cnt[2] += __popc(accm) >> 3;
-    if (out != oldw) *(uint32_t*)(a.sigma + (size_t)A * N + c0) = out;
+    if (out != oldw) __builtin_amdgcn_raw_buffer_store_b32(out, plane_rsrc(a.sigma + (size_t)A * N, N), (int)c0, 0, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
