@@ -107,3 +107,40 @@ def test_cvf3_paper_size(c3, oracle_mod):
     and one full step bit for bit."""
     op = oracle_mod.params_from_si(300.0, 0.1, L=260, seed=2026)
     run3(c3, oracle_mod, op, [1])
+
+
+@pytest.mark.parametrize("L", [1288, 1290])
+def test_cvf3_max_size(c3, oracle_mod, L):
+    """The largest lattices (N = L^3 < 2^31; 1288 runs the quad pass and the
+    two-cube eta kernel, 1290 the pair pass and the one-cube kernel): the
+    initial bond indices of sampled cells equal the oracle's definition
+    (Philox(c, 0, sub, INIT) words), and after one step the incremental
+    counters equal the recount, every sampled molecule has four eta = 1
+    edges and all N/4 cubes and 6N bond indices were attempted."""
+    import torch
+    from paper_2505_05919_amd import cvf
+    op = oracle_mod.params_from_si(300.0, 0.1, L=L, seed=4242)
+    say(f"case max size L={L}")
+    ch = c3.Chain3(gpu_params(cvf, op))
+    N = L ** 3
+    rng = np.random.default_rng(L)
+    cells = np.concatenate([rng.integers(0, N, 300), [0, 1, L - 1, L, N - L * L, N - 2, N - 1]]).astype(np.int64)
+    idx = torch.from_numpy(np.concatenate([cells + b * N for b in range(6)])).cuda()
+    got = ch.sigma[idx].cpu().numpy().reshape(6, -1)
+    for k, c in enumerate(cells):
+        w0 = oracle_mod.philox([int(c), 0, 0, 0], op.seed)
+        w1 = oracle_mod.philox([int(c), 0, 1, 0], op.seed)
+        want = [(int(w) * op.q) >> 32 for w in (w0[0], w0[1], w0[2], w0[3], w1[0], w1[1])]
+        assert list(got[:, k]) == want, (L, int(c))
+    ch.steps(1)
+    o = ch.obs()
+    assert o["consistent"] == 1 and o["n_eta0"] == N and sum(o["count"]) == 6 * N
+    assert o["met_attempted"] == 6 * N and o["eta_attempted"] == N // 4 and o["step"] == 1
+    x, y, z = cells % L, (cells // L) % L, cells // (L * L)
+    lower = [((x - 1) % L) + L * (y + L * z), x + L * (((y - 1) % L) + L * z), x + L * (y + L * ((z - 1) % L))]
+    eidx = np.concatenate([cells + d * N for d in range(3)] + [lower[d] + d * N for d in range(3)])
+    e = ch.eta[torch.from_numpy(eidx.astype(np.int64)).cuda()].cpu().numpy().reshape(6, -1)
+    assert (e.sum(axis=0) == 4).all()
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
