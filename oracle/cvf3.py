@@ -58,6 +58,10 @@ def lib():
         L.ocvf3_get_sigma.argtypes = [ctypes.c_void_p, u8p]
         L.ocvf3_get_eta.argtypes = [ctypes.c_void_p, u8p]
         L.ocvf3_set_state.argtypes = [ctypes.c_void_p, u8p, u8p]
+        L.ocvf3_sw_steps.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.ocvf3_components.argtypes = [ctypes.c_int32, u32p, u32p]
+        L.ocvf3_get_labels.argtypes = [ctypes.c_void_p, u32p]
+        L.ocvf3_get_mask.argtypes = [ctypes.c_void_p, u32p]
         L.ocvf3_incremental.argtypes = [ctypes.c_void_p, i64p, i64p]
         L.ocvf3_incremental.restype = ctypes.c_int64
         _done = True
@@ -76,6 +80,14 @@ def matchings() -> list:
     out = np.zeros(16, dtype=np.uint16)
     n = lib().ocvf3_matchings(_ptr(out, ctypes.c_uint16))
     return [int(x) for x in out[:n]]
+
+
+def components(L: int, mask: np.ndarray) -> np.ndarray:
+    m = np.ascontiguousarray(mask, dtype=np.uint32)
+    assert m.size == L ** 3
+    lab = np.zeros(6 * L ** 3, dtype=np.uint32)
+    lib().ocvf3_components(L, _ptr(m, ctypes.c_uint32), _ptr(lab, ctypes.c_uint32))
+    return lab
 
 
 def tables(p: Params):
@@ -108,6 +120,20 @@ class Chain3:
     def steps(self, n: int):
         lib().ocvf3_steps(self._s, n)
         return self
+
+    def sw(self, n: int):
+        lib().ocvf3_sw_steps(self._s, n)
+        return self
+
+    def labels(self) -> np.ndarray:
+        out = np.zeros(6 * self.N, dtype=np.uint32)
+        lib().ocvf3_get_labels(self._s, _ptr(out, ctypes.c_uint32))
+        return out
+
+    def mask(self) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.uint32)
+        lib().ocvf3_get_mask(self._s, _ptr(out, ctypes.c_uint32))
+        return out
 
     def obs(self) -> dict:
         o = Obs3()

@@ -159,6 +159,8 @@ struct ocvf3_state {
     uint32_t met[2][3][11];
     uint32_t etab[9];
     uint16_t match[16];
+    uint32_t *mask;     /* [N], last SW step */
+    uint32_t *label;    /* [6N], last SW step */
 };
 
 static void count3(const ocvf3_state *s, int64_t *hb, int64_t *coop, int64_t *cnt, int64_t *eta0)
@@ -240,6 +242,8 @@ void ocvf3_destroy(ocvf3_state *s)
     if (!s) return;
     free(s->sigma);
     free(s->eta);
+    free(s->mask);
+    free(s->label);
     free(s);
 }
 
@@ -420,4 +424,123 @@ int64_t ocvf3_incremental(const ocvf3_state *s, int64_t *n_hb_raw, int64_t *n_co
     *n_hb_raw = s->n_hb_raw;
     *n_coop = s->n_coop;
     return s->t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Swendsen-Wang on the cubic lattice (Sec. II.D).  Links of cell c, bit l  */
+/* of its 18-bit mask: l = 0..2 the covalent link of its +d edge (arm 2d of */
+/* c with arm 2d+1 of the +d neighbour), l = 3..17 the cooperative pairs    */
+/* (a, b), a < b, of its six arms in lexicographic order.  Cooperative: equal */
+/* arms bond with p_sigma = 1 - exp(-beta J_sigma).  Covalent, only in the    */
+/* liquid and on eta = 1 edges: equal facing arms bond with p_eff = 1 -      */
+/* exp(-beta |J_eff|) when J_eff > 0, unequal ones when J_eff < 0.  Link l    */
+/* uses word l mod 4 of Philox(c, t, l / 4, SWB); thresholds are 64-bit:     */
+/* bond iff word < floor(p 2^32).  Clusters: label = smallest flat index;     */
+/* each draws pick(word 0 of Philox(label, t, 0, SWF), q) (NONE -> 0) and all */
+/* its bond indices shift by it mod q.                                       */
+/* ------------------------------------------------------------------------ */
+static const int pa3[15] = { 0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4 };
+static const int pb3[15] = { 1, 2, 3, 4, 5, 2, 3, 4, 5, 3, 4, 5, 4, 5, 5 };
+
+void ocvf3_components(int32_t L, const uint32_t *mask, uint32_t *label)
+{
+    const int64_t N = (int64_t)L * L * L, V = 6 * N;
+    uint32_t *queue = (uint32_t *)malloc((size_t)V * sizeof(uint32_t));
+    const uint32_t UNSET = 0xFFFFFFFFu;
+    for (int64_t i = 0; i < V; ++i) label[i] = UNSET;
+    for (int64_t start = 0; start < V; ++start) {
+        if (label[start] != UNSET) continue;
+        int64_t head = 0, tail = 0;
+        label[start] = (uint32_t)start;
+        queue[tail++] = (uint32_t)start;
+        while (head < tail) {
+            const int64_t idx = queue[head++];
+            const int a = (int)(idx / N);
+            const int64_t c = idx % N;
+            int64_t nbr[6];
+            int nn = 0;
+            for (int l = 0; l < 15; ++l) {
+                if (!(mask[c] >> (3 + l) & 1)) continue;
+                if (pa3[l] == a) nbr[nn++] = pb3[l] * N + c;
+                else if (pb3[l] == a) nbr[nn++] = pa3[l] * N + c;
+            }
+            const int d = a >> 1;
+            if ((a & 1) == 0) {                      /* arm +d: link bit d of c */
+                if (mask[c] >> d & 1) nbr[nn++] = (a + 1) * N + nb3(L, c, a);
+            } else {                                 /* arm -d: link bit d of the -d neighbour */
+                const int64_t o = nb3(L, c, a);
+                if (mask[o] >> d & 1) nbr[nn++] = (a - 1) * N + o;
+            }
+            for (int i = 0; i < nn; ++i) {
+                if (label[nbr[i]] == UNSET) {
+                    label[nbr[i]] = (uint32_t)start;
+                    queue[tail++] = (uint32_t)nbr[i];
+                }
+            }
+        }
+    }
+    free(queue);
+}
+
+static void sw3_update(ocvf3_state *s)
+{
+    const int32_t L = s->p.L, q = s->p.q;
+    const int64_t N = s->N;
+    uint8_t *sg = s->sigma;
+    const double Jeff = s->p.J - s->p.P * s->p.vHB;
+    const double xs = s->p.beta * s->p.Jsigma, xe = s->p.beta * fabs(Jeff);
+    const uint64_t thr_sigma = xs > 0.0 ? (uint64_t)floor(-expm1(-xs) * 4294967296.0) : 0;
+    const uint64_t thr_eff = (s->theta && xe > 0.0) ? (uint64_t)floor(-expm1(-xe) * 4294967296.0) : 0;
+    if (!s->mask) s->mask = (uint32_t *)calloc((size_t)N, sizeof(uint32_t));
+    if (!s->label) s->label = (uint32_t *)calloc((size_t)(6 * N), sizeof(uint32_t));
+    for (int64_t c = 0; c < N; ++c) {
+        uint32_t w[20];
+        for (int b = 0; b < 5; ++b) philox((uint32_t)c, (uint32_t)s->t, (uint32_t)b, OCVF_SWB, s->p.seed, w + 4 * b);
+        uint32_t m = 0;
+        for (int d = 0; d < 3; ++d) {
+            const int eq = sg[(2 * d) * N + c] == sg[(2 * d + 1) * N + nb3(L, c, 2 * d)];
+            int bond = 0;
+            if (s->theta && s->eta[d * N + c]) {
+                if (Jeff > 0.0) bond = eq && (uint64_t)w[d] < thr_eff;
+                else if (Jeff < 0.0) bond = !eq && (uint64_t)w[d] < thr_eff;
+            }
+            if (bond) m |= 1u << d;
+        }
+        for (int l = 0; l < 15; ++l) {
+            const int eq = sg[pa3[l] * N + c] == sg[pb3[l] * N + c];
+            if (eq && (uint64_t)w[3 + l] < thr_sigma) m |= 1u << (3 + l);
+        }
+        s->mask[c] = m;
+    }
+    ocvf3_components(L, s->mask, s->label);
+    for (int64_t idx = 0; idx < 6 * N; ++idx) {
+        uint32_t w[4];
+        philox(s->label[idx], (uint32_t)s->t, 0, OCVF_SWF, s->p.seed, w);
+        int32_t r = ocvf_pick(w[0], (uint32_t)q);
+        if (r < 0) r = 0;
+        sg[idx] = (uint8_t)((sg[idx] + r) % q);
+    }
+    count3(s, &s->n_hb_raw, &s->n_coop, NULL, NULL);
+}
+
+void ocvf3_sw_steps(ocvf3_state *s, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        volume_move3(s);
+        eta_update(s);
+        sw3_update(s);
+        s->t++;
+    }
+}
+
+void ocvf3_get_labels(const ocvf3_state *s, uint32_t *out)
+{
+    if (s->label) memcpy(out, s->label, (size_t)(6 * s->N) * sizeof(uint32_t));
+    else memset(out, 0, (size_t)(6 * s->N) * sizeof(uint32_t));
+}
+
+void ocvf3_get_mask(const ocvf3_state *s, uint32_t *out)
+{
+    if (s->mask) memcpy(out, s->mask, (size_t)s->N * sizeof(uint32_t));
+    else memset(out, 0, (size_t)s->N * sizeof(uint32_t));
 }

@@ -62,6 +62,14 @@ void     ocvf3_domain_order(const ocvf_params *p, uint32_t t, int32_t order[6]);
 ocvf3_state *ocvf3_create(const ocvf_params *p);
 void     ocvf3_destroy(ocvf3_state *s);
 void     ocvf3_steps(ocvf3_state *s, int64_t n);
+/* Swendsen-Wang steps: volume move, eta update, then one SW update of sigma
+ * (Sec. II.D on the cubic lattice). */
+void     ocvf3_sw_steps(ocvf3_state *s, int64_t n);
+/* connected components of the 6N bond indices under a per-cell 18-bit link
+ * mask: label = smallest flat index of the cluster */
+void     ocvf3_components(int32_t L, const uint32_t *mask, uint32_t *label);
+void     ocvf3_get_labels(const ocvf3_state *s, uint32_t *out);   /* 6N, last SW step */
+void     ocvf3_get_mask(const ocvf3_state *s, uint32_t *out);     /* N, last SW step  */
 void     ocvf3_observables(const ocvf3_state *s, ocvf3_obs *out);
 void     ocvf3_get_sigma(const ocvf3_state *s, uint8_t *out);   /* 6N bytes */
 void     ocvf3_get_eta(const ocvf3_state *s, uint8_t *out);     /* 3N bytes */

@@ -262,3 +262,93 @@ def test_volume_move_samples_npt_density():
     w = np.exp(f - f.max())
     expect = float((w * v).sum() / w.sum())
     assert abs(m - expect) < 4 * err + 1e-4, (m, expect, err)
+
+
+# ---------------------------------------------------------------- Swendsen-Wang
+PAIRS = [(a, b) for a in range(6) for b in range(a + 1, 6)]
+
+
+@pytest.mark.parametrize("L,density", [(2, 0.3), (4, 0.15), (4, 0.5), (6, 0.08)])
+def test_sw_components_against_scipy(L, density):
+    """Clusters of the 6N bond indices under random 18-bit link masks equal
+    scipy's connected components, each labelled by its smallest flat index."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    N = L ** 3
+    rng = np.random.default_rng(L * 100 + int(density * 100))
+    bits = rng.random((N, 18)) < density
+    mask = (bits * (1 << np.arange(18))).sum(axis=1).astype(np.uint32)
+    rows, cols = [], []
+    for c in range(N):
+        x, y, z = c % L, (c // L) % L, c // (L * L)
+        for d in range(3):
+            if bits[c, d]:
+                o = [x, y, z]
+                o[d] = (o[d] + 1) % L
+                rows.append((2 * d) * N + c)
+                cols.append((2 * d + 1) * N + o[0] + L * (o[1] + L * o[2]))
+        for l, (a, b) in enumerate(PAIRS):
+            if bits[c, 3 + l]:
+                rows.append(a * N + c)
+                cols.append(b * N + c)
+    g = coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(6 * N, 6 * N))
+    _, comp = connected_components(g, directed=False)
+    mins = {}
+    for i, k in enumerate(comp):
+        mins.setdefault(k, i)
+    expect = np.array([mins[k] for k in comp], dtype=np.uint32)
+    assert np.array_equal(cvf3.components(L, mask), expect)
+
+
+def test_sw_closed_form_covalent():
+    """J_sigma = 0: <N_HB_raw> = 2N e^{bJ}/(e^{bJ} + q - 1) under SW as well."""
+    ch = cvf3.Chain3(_params(Jsigma=0.0, beta=0.6, J=2.0, seed=51))
+    m, err = _run_mean_sw(ch, "n_hb_raw", 2000)
+    x = math.exp(0.6 * 2.0)
+    assert abs(m - 2 * ch.N * x / (x + 5)) < 4 * err + 1e-9
+
+
+def test_sw_cooperative_enumeration():
+    ch = cvf3.Chain3(_params(J=0.0, Jsigma=0.5, beta=1.0, seed=52))
+    m, err = _run_mean_sw(ch, "n_coop", 2000)
+    s = np.array(list(itertools.product(range(6), repeat=6)))
+    npairs = sum((s[:, a] == s[:, b]).astype(np.int64) for a in range(6) for b in range(a + 1, 6))
+    w = np.exp(0.5 * npairs)
+    assert abs(m - ch.N * float((w * npairs).sum() / w.sum())) < 4 * err
+
+
+def test_sw_agrees_with_metropolis():
+    """Both updates sample Eq. (3)'s weight: at the paper's parameters (cold
+    liquid, J_eff > 0, eta moving) their <N_HB_raw> and <N_sigma> agree."""
+    p = oracle.params_from_si(250.0, 0.1, L=4, seed=53, flags=oracle.NO_VOLUME_MOVE)
+    res = {}
+    for kind in ("met", "sw"):
+        for key in ("n_hb_raw", "n_coop"):
+            ch = cvf3.Chain3(p)
+            res[kind, key] = _run_mean_sw(ch, key, 3000) if kind == "sw" else _run_mean(ch, key, 3000)
+    for key in ("n_hb_raw", "n_coop"):
+        (a, ea), (b, eb) = res["met", key], res["sw", key]
+        assert abs(a - b) < 4 * math.hypot(ea, eb) + 1e-9, (key, a, b, ea, eb)
+
+
+def test_sw_step_keeps_invariants():
+    ch = cvf3.Chain3(oracle.params_from_si(230.0, 0.1, L=4, seed=54))
+    for _ in range(5):
+        ch.sw(2)
+        t, hb, coop = ch.incremental()
+        o = ch.obs()
+        assert (hb, coop) == (o["n_hb_raw"], o["n_coop"]) and o["n_eta0"] == ch.N
+        lab = ch.labels()
+        assert (lab <= np.arange(6 * ch.N)).all()
+        assert (lab[lab] == lab).all()                           # labels are roots
+
+
+def _run_mean_sw(ch, key, steps, burn=200):
+    ch.sw(burn)
+    xs = []
+    for _ in range(steps):
+        ch.sw(1)
+        xs.append(ch.obs()[key])
+    x = np.asarray(xs, dtype=np.float64)
+    b = x[: len(x) // 20 * 20].reshape(20, -1).mean(axis=1)
+    return x.mean(), b.std(ddof=1) / math.sqrt(20)
