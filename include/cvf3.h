@@ -67,8 +67,11 @@ typedef struct cvf3_obs {
 typedef struct cvf3_state cvf3_state;
 
 /* Workspace size for params p (L even, 2..CVF3_MAX_L; q 2..6; the rest as
- * for cvf_init).  CVF_EINVAL on invalid parameters or a NULL bytes. */
-int cvf3_workspace_bytes(const cvf_params *p, size_t *bytes);
+ * for cvf_init) and the algorithms the chain will run (algo_mask:
+ * CVF_ALGO_METROPOLIS | CVF_ALGO_SW).  Metropolis needs a few KB; SW adds
+ * 4N bytes of link masks and 24N bytes of labels and needs 6N < 2^32
+ * (L <= 894).  CVF_EINVAL on invalid parameters, mask or a NULL bytes. */
+int cvf3_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
 /* Host-only: the tables the kernels use -- met[th][dh+1][dc+5] (sigma move,
  * 32-bit acceptance thresholds, 2^32-1 = always), eta[dn+4] (eta move in the
@@ -83,12 +86,27 @@ int cvf3_tables(const cvf_params *p, uint32_t met[2][3][11], uint32_t eta[9], ui
  * N_HB_raw and N_sigma.  Synchronises the stream.  Errors: CVF_EINVAL
  * (parameters, NULL or misaligned pointers), CVF_ENOMEM (work_bytes too
  * small or host allocation), CVF_EHIP. */
-int cvf3_init(const cvf_params *p, uint8_t *d_sigma, uint8_t *d_eta, void *d_work, size_t work_bytes,
-              void *stream, cvf3_state **out);
+int cvf3_init(const cvf_params *p, int algo_mask, uint8_t *d_sigma, uint8_t *d_eta, void *d_work,
+              size_t work_bytes, void *stream, cvf3_state **out);
 
 /* nsteps MC steps (volume, eta, six sigma passes each).  CVF_EINVAL for a
  * NULL state or nsteps < 0, CVF_EHIP if a launch fails. */
 int cvf3_steps(cvf3_state *st, int64_t nsteps, void *stream);
+
+/* nsteps Swendsen-Wang steps (Sec. II.B order: volume move, eta move, then
+ * one SW update of sigma, Sec. II.D): links per cell -- the 15 cooperative
+ * pairs (equal arms, p = 1 - exp(-beta J_sigma)) and the three covalent
+ * links of its +x, +y, +z edges (liquid and eta = 1 only; equal facing arms
+ * for J_eff > 0, unequal for J_eff < 0, p = 1 - exp(-beta |J_eff|)) --
+ * clusters of the 6N bond indices labelled by their smallest flat index,
+ * one uniform shift per cluster from Philox(label, t, 0, SWF).  CVF_ESTATE
+ * if the chain was created without CVF_ALGO_SW. */
+int cvf3_sw_steps(cvf3_state *st, int64_t nsteps, void *stream);
+
+/* Cluster labels of the last SW step (6N uint32, the smallest flat index of
+ * each bond index's cluster) into d_out.  CVF_ESTATE before the first SW
+ * step or without CVF_ALGO_SW. */
+int cvf3_labels(cvf3_state *st, uint32_t *d_out, void *stream);
 
 /* Observables of the current state from a full recount, with the chain's
  * counters; `consistent` compares the incrementally kept N_HB_raw, N_sigma
@@ -100,7 +118,10 @@ int cvf3_observables(cvf3_state *st, cvf3_obs *out, void *stream);
 #define CVF3_K_VOLUME 0     /* counter fold + volume move + pass order */
 #define CVF3_K_ETA    1     /* eta move over the checkerboard cubes    */
 #define CVF3_K_PASS   2     /* one arm-domain sigma pass               */
-#define CVF3_K_COUNT  3
+#define CVF3_K_SW_BONDS 3   /* SW link masks                           */
+#define CVF3_K_SW_UNION 4   /* SW union-find over the links            */
+#define CVF3_K_SW_FLIP  5   /* SW cluster shift + recount              */
+#define CVF3_K_COUNT  6
 int cvf3_timing_enable(cvf3_state *st, int enable);
 int cvf3_kernel_times(cvf3_state *st, int kind, int64_t *launches, double *mean_ms);
 

@@ -29,7 +29,7 @@ namespace {
 
 #include "philox.h"
 
-constexpr uint32_t kInit = 0, kVol = 1, kOrd = 5, kDom = 6, kEta = 7;
+constexpr uint32_t kInit = 0, kVol = 1, kSwb = 3, kSwf = 4, kOrd = 5, kDom = 6, kEta = 7;
 constexpr int kSlots = 256;              // counter slots, spread to avoid one hot atomic
 constexpr int kAcc = 4;                  // d N_HB_raw, d N_sigma, sigma accepted, eta accepted
 constexpr int kRc = 10;                  // recount: N_HB_raw, N_sigma, N_q' (6), eta = 0 edges, spare
@@ -50,6 +50,8 @@ struct Tab3 {
     uint32_t met[2][3][11];   // sigma move: [theta*eta][dh+1][dc+5]
     uint32_t eta[9];          // eta move in the liquid: [dn+4]
     uint32_t match[9];        // perfect matchings of the cube graph (12-bit edge masks, eta = 0)
+    uint64_t sw_sigma, sw_eff; // SW bond thresholds floor(p 2^32): cooperative, covalent (liquid)
+    int32_t  jeff_sign;        // sign of J_eff
     double   r3[40];          // r3(m), m = 0..36
 };
 
@@ -60,6 +62,8 @@ struct Lat3 {
     int64_t*   slots;         // [kAcc][kSlots]
     int64_t*   rc;            // [kRc][kSlots]
     const Tab3* tab;          // device copy
+    uint32_t*  mask;          // [N] SW link masks (NULL without SW)
+    uint32_t*  par;           // [6N] SW union-find parents, then labels
     uint32_t L, N, h, q;
     uint32_t key0, key1;
     uint32_t pass;
@@ -225,6 +229,8 @@ __global__ void state3_init_kernel(Lat3 a, double v_init)
     }
 }
 
+constexpr int kVolMet = 0, kVolFold = 1, kVolSw = 2;
+
 // ---------------------------------------------------------------------------
 // Counter fold + volume move (Sec. II.B step 1) + pass order of the step.
 // dH = N (u(v') - u(v)) + P N (v' - v) + (theta' - theta)(P v_HB - J) N_HB_raw
@@ -232,7 +238,7 @@ __global__ void state3_init_kernel(Lat3 a, double v_init)
 // with words 0..3 of Philox(0, t, 0, ORD) and word 0 of Philox(0, t, 1, ORD).
 // mode 0: full step opening; mode 1: fold only.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int fold_only)
+__global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int mode)
 {
     __shared__ int64_t part[kAcc][kBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int fold_only)
     s->n_coop += tot[1];
     s->met_acc += tot[2];
     s->eta_acc += tot[3];
-    if (fold_only) return;
+    if (mode == kVolFold) return;
     const uint32_t t = (uint32_t)s->t_next;
     if (a.do_volume) {
         const uint4 w = philox(0u, t, 0u, kVol, a.key0, a.key1);
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int fold_only)
     for (int i = 0; i < 6; ++i) s->order[i] = ord[i];
     s->t_cur = t;
     s->t_next += 1;
-    s->met_att += 6 * (int64_t)a.N;
+    if (mode == kVolMet) s->met_att += 6 * (int64_t)a.N;
     s->eta_att += a.N / 4;
 }
 
@@ -777,6 +783,172 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
 }
 
 // ---------------------------------------------------------------------------
+// Swendsen-Wang on the cubic lattice (Sec. II.D).  Links of cell c, bit l of
+// its mask: l = 0..2 the covalent link of its +d edge (arm 2d of c with arm
+// 2d+1 of the +d neighbour; liquid and eta = 1 only; equal arms for
+// J_eff > 0, unequal for J_eff < 0), l = 3..17 the 15 cooperative pairs
+// (a, b), a < b, lexicographic (equal arms).  Link l uses word l mod 4 of
+// Philox(c, t, l / 4, SWB); bond iff word < 64-bit threshold.
+// Clusters by a lock-free union-find over the 6N bond indices: a link hooks
+// the larger of its two roots under the smaller (CAS on a root's own entry),
+// finds halve paths with plain stores of ancestors into non-roots only, so
+// parents only decrease and every component ends with its smallest index as
+// root -- the label the method's fixed point gives.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void sw3_bonds_kernel(Lat3 a)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.N) return;
+    const uint32_t L = a.L, N = a.N, L2 = L * L;
+    const uint32_t t = (uint32_t)a.st->t_cur;
+    const int theta = a.st->theta;
+    uint32_t s[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        s[b] = a.sigma[(size_t)b * N + c];
+        a.par[(size_t)b * N + c] = b * N + c;
+    }
+    const uint32_t yz = udiv(c, L, a.invL);
+    const uint32_t x = c - yz * L;
+    const uint32_t z = udiv(yz, L, a.invL);
+    const uint32_t y = yz - z * L;
+    const uint32_t nbr[3] = {x == L - 1 ? c + 1 - L : c + 1, y == L - 1 ? c + L - L2 : c + L,
+                             c + L2 >= N ? c + L2 - N : c + L2};
+    uint32_t w[20];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const uint4 r = philox(c, t, (uint32_t)b, kSwb, a.key0, a.key1);
+        w[4 * b] = r.x;
+        w[4 * b + 1] = r.y;
+        w[4 * b + 2] = r.z;
+        w[4 * b + 3] = r.w;
+    }
+    const uint64_t ts = a.tab->sw_sigma, te = theta ? a.tab->sw_eff : 0;
+    const int sgn = a.tab->jeff_sign;
+    uint32_t m = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const bool eq = s[2 * d] == a.sigma[(size_t)(2 * d + 1) * N + nbr[d]];
+        const bool allowed = theta && a.eta[(size_t)d * N + c] != 0;
+        const bool want = sgn > 0 ? eq : (sgn < 0 ? !eq : false);
+        if (allowed && want && (uint64_t)w[d] < te) m |= 1u << d;
+    }
+    int l = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j, ++l)
+            if (s[i] == s[j] && (uint64_t)w[3 + l] < ts) m |= 1u << (3 + l);
+    a.mask[c] = m;
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x)
+{
+    uint32_t p = par[x];
+    while (p != x) {
+        const uint32_t g = par[p];
+        if (g != p) par[x] = g;                            // halve: an ancestor into a non-root
+        x = p;
+        p = g;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void uf_unite(uint32_t* par, uint32_t u, uint32_t v)
+{
+    while (true) {
+        u = uf_find(par, u);
+        v = uf_find(par, v);
+        if (u == v) return;
+        if (u < v) {
+            const uint32_t tmp = u;
+            u = v;
+            v = tmp;
+        }
+        const uint32_t old = atomicCAS(par + u, u, v);    // hook the larger root
+        if (old == u) return;
+        u = old;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.N) return;
+    const uint32_t m = a.mask[c];
+    if (!m) return;
+    const uint32_t L = a.L, N = a.N, L2 = L * L;
+    if (m & 7u) {
+        const uint32_t yz = udiv(c, L, a.invL);
+        const uint32_t x = c - yz * L;
+        const uint32_t z = udiv(yz, L, a.invL);
+        const uint32_t y = yz - z * L;
+        const uint32_t nbr[3] = {x == L - 1 ? c + 1 - L : c + 1, y == L - 1 ? c + L - L2 : c + L,
+                                 c + L2 >= N ? c + L2 - N : c + L2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if ((m >> d) & 1u) uf_unite(a.par, (2 * d) * N + c, (2 * d + 1) * N + nbr[d]);
+    }
+    int l = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j, ++l)
+            if ((m >> (3 + l)) & 1u) uf_unite(a.par, i * N + c, j * N + c);
+}
+
+// Every bond index gets its root (the smallest index of its cluster), and
+// shifts by pick(word 0 of Philox(root, t, 0, SWF), q), NONE -> 0.
+__global__ __launch_bounds__(kBlock) void sw3_flip_kernel(Lat3 a)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 6 * a.N) return;
+    const uint32_t r = uf_find(a.par, i);
+    const uint32_t t = (uint32_t)a.st->t_cur;
+    const uint4 w = philox(r, t, 0u, kSwf, a.key0, a.key1);
+    int k = pick_div(w.x, a.q);
+    if (k < 0) k = 0;
+    uint32_t v = a.sigma[i] + (uint32_t)k;
+    v = v >= a.q ? v - a.q : v;
+    a.sigma[i] = (uint8_t)v;
+}
+
+__global__ __launch_bounds__(kBlock) void sw3_labels_kernel(Lat3 a)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 6 * a.N) return;
+    a.par[i] = uf_find(a.par, i);
+}
+
+// After the flip: the counters become the recount's (slots of the eta move's
+// N_HB_raw change are discarded; accepted-eta counts stay).
+__global__ void sw3_finish_kernel(Lat3 a)
+{
+    __shared__ int64_t part[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t v[2] = {a.rc[threadIdx.x], a.rc[kSlots + threadIdx.x]};
+    a.slots[threadIdx.x] = 0;
+    a.slots[kSlots + threadIdx.x] = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        int64_t sm = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sm += __shfl_xor(sm, o, 64);
+        if (lane == 0) part[k][wv] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t h = 0, c = 0;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            h += part[0][i];
+            c += part[1][i];
+        }
+        a.st->n_hb_raw = h;
+        a.st->n_coop = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Full recount of the configuration (observables): N_HB_raw (eta = 1 edges
 // with equal facing sigma), N_sigma (15 pairs per cell), N_q', eta = 0 edges.
 // ---------------------------------------------------------------------------
@@ -833,6 +1005,8 @@ struct cvf3_state {
     uint8_t*   sigma;
     uint8_t*   eta;
     bool       timing;
+    bool       sw;
+    bool       sw_done;
     std::vector<hipEvent_t> ev[CVF3_K_COUNT];
     int64_t    launches[CVF3_K_COUNT];
     double     total_ms[CVF3_K_COUNT];
@@ -842,8 +1016,16 @@ namespace {
 
 size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-size_t ws3_bytes() { return al256(sizeof(Dev3State)) + al256(sizeof(int64_t) * kAcc * kSlots) +
-                            al256(sizeof(int64_t) * kRc * kSlots) + al256(sizeof(Tab3)); }
+size_t ws3_bytes(const cvf_params* p, int algo_mask)
+{
+    size_t b = al256(sizeof(Dev3State)) + al256(sizeof(int64_t) * kAcc * kSlots) +
+               al256(sizeof(int64_t) * kRc * kSlots) + al256(sizeof(Tab3));
+    if (algo_mask & CVF_ALGO_SW) {
+        const size_t N = (size_t)p->L * p->L * p->L;
+        b += al256(N * sizeof(uint32_t)) + al256(6 * N * sizeof(uint32_t));
+    }
+    return b;
+}
 
 // r3(m): integer points on the sphere i^2 + j^2 + k^2 = m, counted as
 // octant points with signs (each nonzero coordinate doubles the count).
@@ -915,6 +1097,10 @@ void build_tab3(const cvf_params* p, Tab3* t)
                 t->met[th][dh + 1][dc + 5] = thr_of(p->beta, -((double)th * Jeff * (double)dh) - p->Jsigma * (double)dc);
     for (int dn = -4; dn <= 4; ++dn) t->eta[dn + 4] = thr_of(p->beta, -(Jeff * (double)dn));
     cube_matchings(t->match);
+    const double xs = p->beta * p->Jsigma, xe = p->beta * fabs(Jeff);
+    t->sw_sigma = xs > 0.0 ? (uint64_t)floor(-expm1(-xs) * 4294967296.0) : 0;
+    t->sw_eff = xe > 0.0 ? (uint64_t)floor(-expm1(-xe) * 4294967296.0) : 0;
+    t->jeff_sign = Jeff > 0.0 ? 1 : (Jeff < 0.0 ? -1 : 0);
     for (int m = 0; m < 40; ++m) t->r3[m] = m <= 36 ? sphere_points(m) : 0.0;
 }
 
@@ -977,12 +1163,20 @@ int drain3(cvf3_state* st)
 
 extern "C" {
 
-int cvf3_workspace_bytes(const cvf_params* p, size_t* bytes)
+int validate_algo3(const cvf_params* p, int algo_mask)
+{
+    if (algo_mask & ~(CVF_ALGO_METROPOLIS | CVF_ALGO_SW)) return CVF_EINVAL;
+    if ((algo_mask & CVF_ALGO_SW) && 6ull * (uint64_t)p->L * p->L * p->L >= (1ull << 32)) return CVF_EINVAL;
+    return CVF_OK;
+}
+
+int cvf3_workspace_bytes(const cvf_params* p, int algo_mask, size_t* bytes)
 {
     if (!bytes) return CVF_EINVAL;
-    const int rc = validate3(p);
+    int rc = validate3(p);
+    if (rc == CVF_OK) rc = validate_algo3(p, algo_mask);
     if (rc != CVF_OK) return rc;
-    *bytes = ws3_bytes();
+    *bytes = ws3_bytes(p, algo_mask);
     return CVF_OK;
 }
 
@@ -999,16 +1193,17 @@ int cvf3_tables(const cvf_params* p, uint32_t met[2][3][11], uint32_t eta[9], ui
     return CVF_OK;
 }
 
-int cvf3_init(const cvf_params* p, uint8_t* d_sigma, uint8_t* d_eta, void* d_work, size_t work_bytes, void* stream,
-              cvf3_state** out)
+int cvf3_init(const cvf_params* p, int algo_mask, uint8_t* d_sigma, uint8_t* d_eta, void* d_work, size_t work_bytes,
+              void* stream, cvf3_state** out)
 {
     if (!out) return CVF_EINVAL;
     *out = nullptr;
     int rc = validate3(p);
+    if (rc == CVF_OK) rc = validate_algo3(p, algo_mask);
     if (rc != CVF_OK) return rc;
     if (!d_sigma || !d_eta || !d_work) return CVF_EINVAL;
     if (((uintptr_t)d_sigma & 3) || ((uintptr_t)d_eta & 3) || ((uintptr_t)d_work & 255)) return CVF_EINVAL;
-    if (work_bytes < ws3_bytes()) return CVF_ENOMEM;
+    if (work_bytes < ws3_bytes(p, algo_mask)) return CVF_ENOMEM;
     cvf3_state* st = new (std::nothrow) cvf3_state();
     if (!st) return CVF_ENOMEM;
     st->p = *p;
@@ -1027,6 +1222,16 @@ int cvf3_init(const cvf_params* p, uint8_t* d_sigma, uint8_t* d_eta, void* d_wor
     w += al256(sizeof(int64_t) * kRc * kSlots);
     st->dtab = (Tab3*)w;
     a.tab = st->dtab;
+    w += al256(sizeof(Tab3));
+    st->sw = (algo_mask & CVF_ALGO_SW) != 0;
+    a.mask = nullptr;
+    a.par = nullptr;
+    if (st->sw) {
+        const size_t N = (size_t)p->L * p->L * p->L;
+        a.mask = (uint32_t*)w;
+        w += al256(N * sizeof(uint32_t));
+        a.par = (uint32_t*)w;
+    }
     a.L = (uint32_t)p->L;
     a.N = a.L * a.L * a.L;
     a.h = a.L / 2;
@@ -1090,7 +1295,7 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
     Lat3 a = st->la;
     for (int64_t i = 0; i < nsteps; ++i) {
         t_begin(st, CVF3_K_VOLUME, s);
-        vol3_kernel<<<1, kBlock, 0, s>>>(a, 0);
+        vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolMet);
         t_end(st, CVF3_K_VOLUME, s);
         t_begin(st, CVF3_K_ETA, s);
         if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
@@ -1109,12 +1314,58 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
     return CVF_OK;
 }
 
+int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
+{
+    if (!st || nsteps < 0) return CVF_EINVAL;
+    if (!st->sw) return CVF_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    const Lat3& a = st->la;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        t_begin(st, CVF3_K_VOLUME, s);
+        vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolSw);
+        t_end(st, CVF3_K_VOLUME, s);
+        t_begin(st, CVF3_K_ETA, s);
+        if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
+        else eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
+        t_end(st, CVF3_K_ETA, s);
+        t_begin(st, CVF3_K_SW_BONDS, s);
+        sw3_bonds_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        t_end(st, CVF3_K_SW_BONDS, s);
+        t_begin(st, CVF3_K_SW_UNION, s);
+        sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        t_end(st, CVF3_K_SW_UNION, s);
+        t_begin(st, CVF3_K_SW_FLIP, s);
+        sw3_flip_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);
+        zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
+        recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        sw3_finish_kernel<<<1, kBlock, 0, s>>>(a);
+        t_end(st, CVF3_K_SW_FLIP, s);
+        const int rc = hs(hipGetLastError());
+        if (rc != CVF_OK) return rc;
+        st->sw_done = true;
+    }
+    return CVF_OK;
+}
+
+int cvf3_labels(cvf3_state* st, uint32_t* d_out, void* stream)
+{
+    if (!st || !d_out) return CVF_EINVAL;
+    if (!st->sw || !st->sw_done) return CVF_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    const Lat3& a = st->la;
+    sw3_labels_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);
+    int rc = hs(hipGetLastError());
+    if (rc == CVF_OK)
+        rc = hs(hipMemcpyAsync(d_out, a.par, 6ull * a.N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    return rc;
+}
+
 int cvf3_observables(cvf3_state* st, cvf3_obs* out, void* stream)
 {
     if (!st || !out) return CVF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Lat3& a = st->la;
-    vol3_kernel<<<1, kBlock, 0, s>>>(a, 1);
+    vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolFold);
     zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
     recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
     int rc = hs(hipGetLastError());

@@ -10,13 +10,14 @@ import ctypes
 
 import numpy as np
 
-from .cvf import CvfError, _check, _devptr, _stream, cvf_params, lib as _lib
+from .cvf import CVF_ALGO_METROPOLIS, CVF_ALGO_SW, CvfError, _check, _devptr, _stream, cvf_params, lib as _lib
 
 CVF3_MAX_L = 1290
-CVF3_K_VOLUME, CVF3_K_ETA, CVF3_K_PASS, CVF3_K_COUNT = range(4)
+(CVF3_K_VOLUME, CVF3_K_ETA, CVF3_K_PASS, CVF3_K_SW_BONDS, CVF3_K_SW_UNION, CVF3_K_SW_FLIP,
+ CVF3_K_COUNT) = range(7)
 
-EXPORTS = ["cvf3_workspace_bytes", "cvf3_tables", "cvf3_init", "cvf3_steps", "cvf3_observables",
-           "cvf3_timing_enable", "cvf3_kernel_times", "cvf3_destroy"]
+EXPORTS = ["cvf3_workspace_bytes", "cvf3_tables", "cvf3_init", "cvf3_steps", "cvf3_sw_steps", "cvf3_labels",
+           "cvf3_observables", "cvf3_timing_enable", "cvf3_kernel_times", "cvf3_destroy"]
 
 
 class cvf3_obs(ctypes.Structure):
@@ -43,10 +44,12 @@ def lib():
     if not _done:
         vp, P = ctypes.c_void_p, ctypes.POINTER(cvf_params)
         u32p = ctypes.POINTER(ctypes.c_uint32)
-        L.cvf3_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.cvf3_workspace_bytes.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.cvf3_tables.argtypes = [P, u32p, u32p, u32p]
-        L.cvf3_init.argtypes = [P, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.cvf3_init.argtypes = [P, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.cvf3_steps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf3_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
+        L.cvf3_labels.argtypes = [vp, vp, vp]
         L.cvf3_observables.argtypes = [vp, ctypes.POINTER(cvf3_obs), vp]
         L.cvf3_timing_enable.argtypes = [vp, ctypes.c_int]
         L.cvf3_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
@@ -58,9 +61,9 @@ def lib():
     return L
 
 
-def cvf3_workspace_bytes(p: cvf_params) -> int:
+def cvf3_workspace_bytes(p: cvf_params, algo_mask: int = CVF_ALGO_METROPOLIS) -> int:
     n = ctypes.c_size_t()
-    _check("cvf3_workspace_bytes", lib().cvf3_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    _check("cvf3_workspace_bytes", lib().cvf3_workspace_bytes(ctypes.byref(p), algo_mask, ctypes.byref(n)))
     return n.value
 
 
@@ -75,18 +78,31 @@ def cvf3_tables(p: cvf_params):
     return met, eta, match
 
 
-def cvf3_init(p: cvf_params, sigma, eta, work, stream=None):
+def cvf3_init(p: cvf_params, sigma, eta, work, stream=None, algo_mask: int = CVF_ALGO_METROPOLIS):
     N = p.L ** 3
     sp, _ = _devptr(sigma, "torch.uint8", 6 * N)
     ep, _ = _devptr(eta, "torch.uint8", 3 * N)
     wp, wn = _devptr(work, "torch.uint8", 1)
     h = ctypes.c_void_p()
-    _check("cvf3_init", lib().cvf3_init(ctypes.byref(p), sp, ep, wp, wn, _stream(stream), ctypes.byref(h)))
+    _check("cvf3_init", lib().cvf3_init(ctypes.byref(p), algo_mask, sp, ep, wp, wn, _stream(stream), ctypes.byref(h)))
     return h
 
 
 def cvf3_steps(h, nsteps: int, stream=None):
     _check("cvf3_steps", lib().cvf3_steps(h, nsteps, _stream(stream)))
+
+
+def cvf3_sw_steps(h, nsteps: int, stream=None):
+    _check("cvf3_sw_steps", lib().cvf3_sw_steps(h, nsteps, _stream(stream)))
+
+
+def cvf3_labels(h, out, stream=None):
+    """Labels of the last SW step into `out` (a GPU int32 tensor of 6N; the
+    values are uint32 cluster minima, read them with .view(torch.uint32)
+    or numpy .view(np.uint32))."""
+    op, _ = _devptr(out, "torch.int32", out.numel() * 4)
+    _check("cvf3_labels", lib().cvf3_labels(h, op, _stream(stream)))
+    return out
 
 
 def cvf3_observables(h, stream=None) -> dict:
@@ -113,19 +129,28 @@ class Chain3:
     """Owner of one cubic-lattice chain's device buffers (sigma 6N, eta 3N,
     workspace) and its library handle."""
 
-    def __init__(self, p: cvf_params, stream=None, sigma=None, eta=None):
+    def __init__(self, p: cvf_params, stream=None, sigma=None, eta=None, algo_mask: int = CVF_ALGO_METROPOLIS):
         import torch
         self.p = cvf_params.from_buffer_copy(p)
         self.N = p.L ** 3
         self.sigma = sigma if sigma is not None else torch.empty(6 * self.N, dtype=torch.uint8, device="cuda")
         self.eta = eta if eta is not None else torch.empty(3 * self.N, dtype=torch.uint8, device="cuda")
-        self.work = torch.empty(cvf3_workspace_bytes(self.p), dtype=torch.uint8, device="cuda")
+        self.work = torch.empty(cvf3_workspace_bytes(self.p, algo_mask), dtype=torch.uint8, device="cuda")
         self.stream = stream
-        self.h = cvf3_init(self.p, self.sigma, self.eta, self.work, stream)
+        self.h = cvf3_init(self.p, self.sigma, self.eta, self.work, stream, algo_mask)
 
     def steps(self, n):
         cvf3_steps(self.h, n, self.stream)
         return self
+
+    def sw(self, n):
+        cvf3_sw_steps(self.h, n, self.stream)
+        return self
+
+    def labels(self):
+        import torch
+        out = torch.empty(6 * self.N, dtype=torch.int32, device=self.sigma.device)
+        return cvf3_labels(self.h, out, self.stream)
 
     def obs(self):
         return cvf3_observables(self.h, self.stream)

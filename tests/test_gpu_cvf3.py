@@ -144,3 +144,70 @@ def test_cvf3_max_size(c3, oracle_mod, L):
     ch.close()
     del ch
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- Swendsen-Wang
+def run3_mixed(c3, oracle_mod, op, plan):
+    """plan: ("met" | "sw", n) items applied to both; sigma, eta, counters and
+    (after SW) the cluster labels compared after each item."""
+    from oracle import cvf3 as o3
+    from paper_2505_05919_amd import cvf
+    ctx = f"L={op.L} q={op.q} seed={op.seed} beta={op.beta:.6g} P={op.P:.6g} v0={op.v_init} plan={plan}"
+    say("case " + ctx)
+    ch = c3.Chain3(gpu_params(cvf, op), algo_mask=cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+    oc = o3.Chain3(op)
+    compare(ch, oc, ctx + " init")
+    for kind, n in plan:
+        if kind == "sw":
+            ch.sw(n)
+            oc.sw(n)
+        else:
+            ch.steps(n)
+            oc.steps(n)
+        og = compare(ch, oc, f"{ctx} after {kind} {n}")
+        if kind == "sw":
+            assert np.array_equal(ch.labels().cpu().numpy().view(np.uint32), oc.labels()), ctx + " labels"
+    ch.close()
+    return og
+
+
+@pytest.mark.parametrize("L,n", [(2, 10), (4, 6), (6, 4), (8, 3), (16, 2), (18, 2), (36, 1)])
+def test_cvf3_sw_parity(c3, oracle_mod, L, n):
+    op = oracle_mod.params_from_si(230.0, 0.1, L=L, seed=900 + L)
+    run3_mixed(c3, oracle_mod, op, [("sw", 1), ("sw", n)])
+
+
+@pytest.mark.parametrize("T,P,v0", [(195.0, 0.1, 1.1), (330.0, 0.1, 2.5), (300.0, 1500.0, 1.2), (400.0, -200.0, 1.9)])
+def test_cvf3_sw_state_points(c3, oracle_mod, T, P, v0):
+    """Near-percolating cold liquid, gas (no covalent links), J_eff < 0
+    (unequal facing arms bond) and a volume crossing v = 2."""
+    op = oracle_mod.params_from_si(T, P, L=10, seed=int(T) + 7, v_init=v0, dv_max=0.3 if v0 == 1.9 else 0.0125)
+    run3_mixed(c3, oracle_mod, op, [("sw", 2), ("sw", 4)])
+
+
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_cvf3_sw_reduced_q_mixed(c3, oracle_mod, q):
+    op = oracle_mod.params_from_si(240.0, 25.0, L=12, q=q, seed=950 + q)
+    run3_mixed(c3, oracle_mod, op, [("sw", 2), ("met", 2), ("sw", 2)])
+
+
+def test_cvf3_sw_paper_size(c3, oracle_mod):
+    """N = 128^3 = 2 097 152, the paper's largest SW lattice: two steps bit
+    for bit, labels included."""
+    op = oracle_mod.params_from_si(210.0, 0.1, L=128, seed=2048)
+    run3_mixed(c3, oracle_mod, op, [("sw", 2)])
+
+
+def test_cvf3_sw_state_errors(c3, oracle_mod):
+    from paper_2505_05919_amd import cvf
+    op = oracle_mod.params_from_si(300.0, 0.1, L=4, seed=1)
+    ch = c3.Chain3(gpu_params(cvf, op))                      # Metropolis only
+    with pytest.raises(cvf.CvfError) as e:
+        ch.sw(1)
+    assert e.value.code == cvf.CVF_ESTATE
+    ch.close()
+    ch = c3.Chain3(gpu_params(cvf, op), algo_mask=cvf.CVF_ALGO_SW)
+    with pytest.raises(cvf.CvfError) as e:
+        ch.labels()                                          # before the first SW step
+    assert e.value.code == cvf.CVF_ESTATE
+    ch.close()
