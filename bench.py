@@ -154,7 +154,34 @@ def bench_cvf3(torch, W, K, L=260):
                               "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": BYTES_3D,
                               "alu": {"achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                                       "frac": round(tops / VALU_PEAK_TOPS, 4), "ops_per_update": ALU_OPS_3D}},
-            "paper_rtx3060_ms_per_step": 280.0}
+            "paper_rtx3060_ms_per_step": 280.0,
+            "sw": bench_cvf3_sw(torch, W, max(K // 2, 10))}
+
+
+def bench_cvf3_sw(torch, W, K, L=128):
+    """Swendsen-Wang on the cubic lattice with eta at the paper's SW size,
+    N = 128^3 = 2 097 152 (volume move + eta moves + SW update per step)."""
+    from paper_2505_05919_amd import cvf, cvf3
+    p = cvf.cvf_params_from_si(210.0, 0.1, L=L, seed=2048)
+    ch = cvf3.Chain3(p, algo_mask=cvf.CVF_ALGO_SW)
+    ch.sw(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.sw(K)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cvf3.cvf3_timing_enable(ch.h, True)
+    ch.sw(K)
+    kinds = {"volume": cvf3.CVF3_K_VOLUME, "eta": cvf3.CVF3_K_ETA, "bonds": cvf3.CVF3_K_SW_BONDS,
+             "union": cvf3.CVF3_K_SW_UNION, "flip_recount": cvf3.CVF3_K_SW_FLIP}
+    kt = {nm: round(cvf3.cvf3_kernel_times(ch.h, k)[1] * 1e3, 2) for nm, k in kinds.items()}
+    cvf3.cvf3_timing_enable(ch.h, False)
+    o = ch.obs()
+    assert o["consistent"] == 1 and o["n_eta0"] == L ** 3
+    ch.close()
+    return {"L": L, "N": L ** 3, "T_K": 210.0, "steps": K, "steps_per_s": round(K / t, 1),
+            "ms_per_step": round(t / K * 1e3, 4), "kernel_mean_us": kt,
+            "paper_rtx3060_steps_per_s_fit_bound": 13.1}
 
 
 def cpu_baseline(budget_s: float):

@@ -804,10 +804,7 @@ __global__ __launch_bounds__(kBlock) void sw3_bonds_kernel(Lat3 a)
     const int theta = a.st->theta;
     uint32_t s[6];
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
-        s[b] = a.sigma[(size_t)b * N + c];
-        a.par[(size_t)b * N + c] = b * N + c;
-    }
+    for (int b = 0; b < 6; ++b) s[b] = a.sigma[(size_t)b * N + c];
     const uint32_t yz = udiv(c, L, a.invL);
     const uint32_t x = c - yz * L;
     const uint32_t z = udiv(yz, L, a.invL);
@@ -840,6 +837,29 @@ __global__ __launch_bounds__(kBlock) void sw3_bonds_kernel(Lat3 a)
         for (int j = i + 1; j < 6; ++j, ++l)
             if (s[i] == s[j] && (uint64_t)w[3 + l] < ts) m |= 1u << (3 + l);
     a.mask[c] = m;
+    // The cooperative links join arms of this cell only: their components
+    // (transitive closure of the six arms' adjacency, Warshall's order) are
+    // resolved here, each arm's parent set to the smallest arm of its
+    // component -- the smallest flat index, since arm a of c is a N + c.
+    uint32_t comp[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) comp[i] = 1u << i;
+    l = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j, ++l)
+            if ((m >> (3 + l)) & 1u) {
+                comp[i] |= 1u << j;
+                comp[j] |= 1u << i;
+            }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if ((comp[i] >> k) & 1u) comp[i] |= comp[k];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) a.par[(size_t)b * N + c] = (uint32_t)(__builtin_ctz(comp[b])) * N + c;
 }
 
 __device__ __forceinline__ uint32_t uf_find(uint32_t* par, uint32_t x)
@@ -875,10 +895,10 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a)
 {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.N) return;
-    const uint32_t m = a.mask[c];
+    const uint32_t m = a.mask[c] & 7u;                  // covalent links; cooperative ones are resolved
     if (!m) return;
     const uint32_t L = a.L, N = a.N, L2 = L * L;
-    if (m & 7u) {
+    {
         const uint32_t yz = udiv(c, L, a.invL);
         const uint32_t x = c - yz * L;
         const uint32_t z = udiv(yz, L, a.invL);
@@ -889,12 +909,6 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a)
         for (int d = 0; d < 3; ++d)
             if ((m >> d) & 1u) uf_unite(a.par, (2 * d) * N + c, (2 * d + 1) * N + nbr[d]);
     }
-    int l = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = i + 1; j < 6; ++j, ++l)
-            if ((m >> (3 + l)) & 1u) uf_unite(a.par, i * N + c, j * N + c);
 }
 
 // Every bond index gets its root (the smallest index of its cluster), and
@@ -913,11 +927,20 @@ __global__ __launch_bounds__(kBlock) void sw3_flip_kernel(Lat3 a)
     a.sigma[i] = (uint8_t)v;
 }
 
+// Flattening in place: each lane stores only its own entry, and finds here
+// never write (a halving store by another lane could otherwise overwrite an
+// entry already flattened with an ancestor short of the root); concurrent
+// readers see either the old parent or the root, both on the path.
 __global__ __launch_bounds__(kBlock) void sw3_labels_kernel(Lat3 a)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= 6 * a.N) return;
-    a.par[i] = uf_find(a.par, i);
+    uint32_t x = i, p = a.par[x];
+    while (p != x) {
+        x = p;
+        p = a.par[x];
+    }
+    a.par[i] = x;
 }
 
 // After the flip: the counters become the recount's (slots of the eta move's
