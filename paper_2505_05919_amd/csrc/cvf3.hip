@@ -891,11 +891,81 @@ __device__ __forceinline__ void uf_unite(uint32_t* par, uint32_t u, uint32_t v)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a)
+// Tile phase (L % 8 == 0): one workgroup per 8 x 8 x 4 cells.  Its 6 x 256
+// bond indices get local indices a*256 + lx + 8 (ly + 8 lz), which order
+// them as their flat indices a N + c do, so the same rule (hook the larger
+// root under the smaller, CAS in LDS) leaves every in-tile component rooted
+// at its smallest flat index.  Covalent links inside the tile are united
+// here; each bond index's global parent becomes its in-tile root, and only
+// links that cross a tile face remain for sw3_union_kernel.
+__device__ __forceinline__ uint32_t lds_find(uint32_t* lp, uint32_t x)
+{
+    uint32_t p = lp[x];
+    while (p != x) {
+        const uint32_t g = lp[p];
+        if (g != p) lp[x] = g;
+        x = p;
+        p = g;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_unite(uint32_t* lp, uint32_t u, uint32_t v)
+{
+    while (true) {
+        u = lds_find(lp, u);
+        v = lds_find(lp, v);
+        if (u == v) return;
+        if (u < v) {
+            const uint32_t tmp = u;
+            u = v;
+            v = tmp;
+        }
+        const uint32_t old = atomicCAS(lp + u, u, v);
+        if (old == u) return;
+        u = old;
+    }
+}
+
+__global__ __launch_bounds__(256) void sw3_tile_union_kernel(Lat3 a)
+{
+    __shared__ uint32_t lp[6 * 256];
+    const uint32_t L = a.L, N = a.N;
+    const uint32_t tx = L / 8, ty = L / 8;
+    const uint32_t b = blockIdx.x;
+    const uint32_t bx = b % tx, by = (b / tx) % ty, bz = b / (tx * ty);
+    const uint32_t t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const uint32_t c = (8 * bx + lx) + L * ((8 * by + ly) + L * (4 * bz + lz));
+    // in-cell roots from the bonds kernel: parent of arm k is arm r of the same cell
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint32_t r = a.par[(size_t)k * N + c] / N;
+        lp[k * 256 + t] = r * 256 + t;
+    }
+    __syncthreads();
+    const uint32_t m = a.mask[c] & 7u;
+    if ((m & 1u) && lx < 7) lds_unite(lp, 0 * 256 + t, 1 * 256 + t + 1);
+    if ((m & 2u) && ly < 7) lds_unite(lp, 2 * 256 + t, 3 * 256 + t + 8);
+    if ((m & 4u) && lz < 3) lds_unite(lp, 4 * 256 + t, 5 * 256 + t + 64);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        uint32_t x = k * 256 + t, q = lp[x];
+        while (q != x) {                                   // read-only: lp is not written any more
+            x = q;
+            q = lp[x];
+        }
+        const uint32_t rt = x & 255u, ra = x >> 8;
+        const uint32_t rc = (8 * bx + (rt & 7)) + L * ((8 * by + ((rt >> 3) & 7)) + L * (4 * bz + (rt >> 6)));
+        a.par[(size_t)k * N + c] = ra * N + rc;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, int tiled)
 {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.N) return;
-    const uint32_t m = a.mask[c] & 7u;                  // covalent links; cooperative ones are resolved
+    uint32_t m = a.mask[c] & 7u;                        // covalent links; cooperative ones are resolved
     if (!m) return;
     const uint32_t L = a.L, N = a.N, L2 = L * L;
     {
@@ -905,6 +975,11 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a)
         const uint32_t y = yz - z * L;
         const uint32_t nbr[3] = {x == L - 1 ? c + 1 - L : c + 1, y == L - 1 ? c + L - L2 : c + L,
                                  c + L2 >= N ? c + L2 - N : c + L2};
+        if (tiled) {                                      // in-tile links were united by the tile phase
+            if ((x & 7) != 7) m &= ~1u;
+            if ((y & 7) != 7) m &= ~2u;
+            if ((z & 3) != 3) m &= ~4u;
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d)
             if ((m >> d) & 1u) uf_unite(a.par, (2 * d) * N + c, (2 * d + 1) * N + nbr[d]);
@@ -1355,7 +1430,9 @@ int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
         sw3_bonds_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
         t_end(st, CVF3_K_SW_BONDS, s);
         t_begin(st, CVF3_K_SW_UNION, s);
-        sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
+        const bool tiled = a.L % 8 == 0;
+        if (tiled) sw3_tile_union_kernel<<<a.N / 256, 256, 0, s>>>(a);
+        sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a, tiled ? 1 : 0);
         t_end(st, CVF3_K_SW_UNION, s);
         t_begin(st, CVF3_K_SW_FLIP, s);
         sw3_flip_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);
