@@ -891,8 +891,8 @@ __device__ __forceinline__ void uf_unite(uint32_t* par, uint32_t u, uint32_t v)
     }
 }
 
-// Tile phase (L % 8 == 0): one workgroup per 8 x 8 x 4 cells.  Its 6 x 256
-// bond indices get local indices a*256 + lx + 8 (ly + 8 lz), which order
+// Tile phase (L % 8 == 0): one workgroup per TX x TY x TZ cells.  Its 6 T
+// bond indices get local indices a T + lx + TX (ly + TY lz), which order
 // them as their flat indices a N + c do, so the same rule (hook the larger
 // root under the smaller, CAS in LDS) leaves every in-tile component rooted
 // at its smallest flat index.  Covalent links inside the tile are united
@@ -927,41 +927,43 @@ __device__ __forceinline__ void lds_unite(uint32_t* lp, uint32_t u, uint32_t v)
     }
 }
 
-__global__ __launch_bounds__(256) void sw3_tile_union_kernel(Lat3 a)
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ) void sw3_tile_union_kernel(Lat3 a)
 {
-    __shared__ uint32_t lp[6 * 256];
+    constexpr uint32_t T = TX * TY * TZ;
+    __shared__ uint32_t lp[6 * T];
     const uint32_t L = a.L, N = a.N;
-    const uint32_t tx = L / 8, ty = L / 8;
+    const uint32_t tx = L / TX, ty = L / TY;
     const uint32_t b = blockIdx.x;
     const uint32_t bx = b % tx, by = (b / tx) % ty, bz = b / (tx * ty);
-    const uint32_t t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const uint32_t c = (8 * bx + lx) + L * ((8 * by + ly) + L * (4 * bz + lz));
+    const uint32_t t = threadIdx.x, lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+    const uint32_t c = (TX * bx + lx) + L * ((TY * by + ly) + L * (TZ * bz + lz));
     // in-cell roots from the bonds kernel: parent of arm k is arm r of the same cell
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const uint32_t r = a.par[(size_t)k * N + c] / N;
-        lp[k * 256 + t] = r * 256 + t;
+        lp[k * T + t] = r * T + t;
     }
     __syncthreads();
     const uint32_t m = a.mask[c] & 7u;
-    if ((m & 1u) && lx < 7) lds_unite(lp, 0 * 256 + t, 1 * 256 + t + 1);
-    if ((m & 2u) && ly < 7) lds_unite(lp, 2 * 256 + t, 3 * 256 + t + 8);
-    if ((m & 4u) && lz < 3) lds_unite(lp, 4 * 256 + t, 5 * 256 + t + 64);
+    if ((m & 1u) && lx < TX - 1) lds_unite(lp, 0 * T + t, 1 * T + t + 1);
+    if ((m & 2u) && ly < TY - 1) lds_unite(lp, 2 * T + t, 3 * T + t + TX);
+    if ((m & 4u) && lz < TZ - 1) lds_unite(lp, 4 * T + t, 5 * T + t + TX * TY);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        uint32_t x = k * 256 + t, q = lp[x];
+        uint32_t x = k * T + t, q = lp[x];
         while (q != x) {                                   // read-only: lp is not written any more
             x = q;
             q = lp[x];
         }
-        const uint32_t rt = x & 255u, ra = x >> 8;
-        const uint32_t rc = (8 * bx + (rt & 7)) + L * ((8 * by + ((rt >> 3) & 7)) + L * (4 * bz + (rt >> 6)));
+        const uint32_t rt = x % T, ra = x / T;
+        const uint32_t rc = (TX * bx + rt % TX) + L * ((TY * by + (rt / TX) % TY) + L * (TZ * bz + rt / (TX * TY)));
         a.par[(size_t)k * N + c] = ra * N + rc;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, int tiled)
+__global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, uint32_t tx_, uint32_t ty_, uint32_t tz_)
 {
     const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= a.N) return;
@@ -975,10 +977,10 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, int tiled)
         const uint32_t y = yz - z * L;
         const uint32_t nbr[3] = {x == L - 1 ? c + 1 - L : c + 1, y == L - 1 ? c + L - L2 : c + L,
                                  c + L2 >= N ? c + L2 - N : c + L2};
-        if (tiled) {                                      // in-tile links were united by the tile phase
-            if ((x & 7) != 7) m &= ~1u;
-            if ((y & 7) != 7) m &= ~2u;
-            if ((z & 3) != 3) m &= ~4u;
+        if (tx_) {                                        // in-tile links were united by the tile phase
+            if (x % tx_ != tx_ - 1) m &= ~1u;
+            if (y % ty_ != ty_ - 1) m &= ~2u;
+            if (z % tz_ != tz_ - 1) m &= ~4u;
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d)
@@ -1430,9 +1432,17 @@ int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
         sw3_bonds_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
         t_end(st, CVF3_K_SW_BONDS, s);
         t_begin(st, CVF3_K_SW_UNION, s);
-        const bool tiled = a.L % 8 == 0;
-        if (tiled) sw3_tile_union_kernel<<<a.N / 256, 256, 0, s>>>(a);
-        sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a, tiled ? 1 : 0);
+        // tile phase: 16 x 8 x 8 cells (a sixteenth of the x links and an
+        // eighth of the y and z links cross a face) or 8 x 8 x 4
+        if (a.L % 16 == 0) {
+            sw3_tile_union_kernel<16, 8, 8><<<a.N / 1024, 1024, 0, s>>>(a);
+            sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a, 16, 8, 8);
+        } else if (a.L % 8 == 0) {
+            sw3_tile_union_kernel<8, 8, 4><<<a.N / 256, 256, 0, s>>>(a);
+            sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a, 8, 8, 4);
+        } else {
+            sw3_union_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a, 0, 0, 0);
+        }
         t_end(st, CVF3_K_SW_UNION, s);
         t_begin(st, CVF3_K_SW_FLIP, s);
         sw3_flip_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);
