@@ -238,50 +238,73 @@ constexpr int kVolMet = 0, kVolFold = 1, kVolSw = 2;
 // with words 0..3 of Philox(0, t, 0, ORD) and word 0 of Philox(0, t, 1, ORD).
 // mode 0: full step opening; mode 1: fold only.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int mode)
+// One wavefront: lanes fold the counter slots (kSlots / 64 each), lanes 0-2
+// draw the VOL block and the two ORD blocks at once, lanes 1..36 evaluate one
+// U_LJ shell term each; lane 0 then sums the terms in ascending shell order
+// up to the first shell beyond the cutoff (the order of lj3) and takes the
+// decisions.
+__global__ __launch_bounds__(64) void vol3_kernel(Lat3 a, int mode)
 {
-    __shared__ int64_t part[kAcc][kBlock / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t v[kAcc];
+    __shared__ double term[40];
+    __shared__ uint32_t words[3][4];
+    const int lane = threadIdx.x;
+    Dev3State* s = a.st;
+    int64_t sl[kAcc];
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) {
-        v[k] = a.slots[k * kSlots + threadIdx.x];
-        a.slots[k * kSlots + threadIdx.x] = 0;
+        sl[k] = 0;
+#pragma unroll
+        for (int j = 0; j < kSlots / 64; ++j) {
+            sl[k] += a.slots[k * kSlots + j * 64 + lane];
+            a.slots[k * kSlots + j * 64 + lane] = 0;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sl[k] += __shfl_xor(sl[k], o, 64);
     }
-#pragma unroll
-    for (int k = 0; k < kAcc; ++k) {
-        int64_t s = v[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) part[k][wv] = s;
+    const uint32_t t = (uint32_t)s->t_next;
+    const double v0 = s->v;
+    if (mode != kVolFold && lane < 3) {
+        const uint4 w = philox(0u, t, lane == 2 ? 1u : 0u, lane == 0 ? kVol : kOrd, a.key0, a.key1);
+        words[lane][0] = w.x;
+        words[lane][1] = w.y;
+        words[lane][2] = w.z;
+        words[lane][3] = w.w;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    int64_t tot[kAcc];
-    for (int k = 0; k < kAcc; ++k) {
-        tot[k] = 0;
-        for (int i = 0; i < kBlock / 64; ++i) tot[k] += part[k][i];
+    double v1 = 0.0;
+    bool inside = false;
+    if (mode != kVolFold && a.do_volume) {
+        const double u = (double)((int64_t)2 * (int64_t)words[0][0] + 1 - 4294967296LL) * (1.0 / 4294967296.0);
+        v1 = v0 + a.dv_max * u;
+        inside = v1 >= 1.0;
+        if (inside && lane >= 1 && lane <= 36) {
+            const double d6 = (v1 * v1) * (double)(lane * lane * lane);
+            const double s6 = 1.0 / d6;
+            term[lane] = d6 <= 46656.0 ? a.tab->r3[lane] * (s6 * s6 - s6) : 0.0;
+        }
     }
-    Dev3State* s = a.st;
-    s->n_hb_raw += tot[0];
-    s->n_coop += tot[1];
-    s->met_acc += tot[2];
-    s->eta_acc += tot[3];
+    __syncthreads();
+    if (lane != 0) return;
+    s->n_hb_raw += sl[0];
+    s->n_coop += sl[1];
+    s->met_acc += sl[2];
+    s->eta_acc += sl[3];
     if (mode == kVolFold) return;
-    const uint32_t t = (uint32_t)s->t_next;
     if (a.do_volume) {
-        const uint4 w = philox(0u, t, 0u, kVol, a.key0, a.key1);
         s->vol_att += 1;
-        const double u = (double)((int64_t)2 * (int64_t)w.x + 1 - 4294967296LL) * (1.0 / 4294967296.0);
-        const double v0 = s->v;
-        const double v1 = v0 + a.dv_max * u;
-        if (v1 >= 1.0) {
-            const double u0 = s->u, u1 = lj3(v1, a.tab->r3);
+        if (inside) {
+            double sum = 0.0;
+            for (int m = 1; m <= 36; ++m) {
+                const double d6 = (v1 * v1) * (double)(m * m * m);
+                if (!(d6 <= 46656.0)) break;
+                sum = sum + term[m];
+            }
+            const double u0 = s->u, u1 = 2.0 * sum;
             const int th0 = s->theta, th1 = v1 < 2.0 ? 1 : 0;
             const double dH = (a.Nd * (u1 - u0)) + ((a.P * a.Nd) * (v1 - v0))
                             + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)s->n_hb_raw);
             bool acc = dH <= 0.0;
-            if (!acc) acc = ((double)w.y + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
+            if (!acc) acc = ((double)words[0][1] + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
             if (acc) {
                 s->v = v1;
                 s->u = u1;
@@ -290,9 +313,7 @@ __global__ __launch_bounds__(kBlock) void vol3_kernel(Lat3 a, int mode)
             }
         }
     }
-    const uint4 o0 = philox(0u, t, 0u, kOrd, a.key0, a.key1);
-    const uint4 o1 = philox(0u, t, 1u, kOrd, a.key0, a.key1);
-    const uint32_t ow[5] = {o0.x, o0.y, o0.z, o0.w, o1.x};
+    const uint32_t ow[5] = {words[1][0], words[1][1], words[1][2], words[1][3], words[2][0]};
     int ord[6] = {0, 1, 2, 3, 4, 5};
     for (int i = 0; i < 5; ++i) {
         int k = pick_div(ow[i], (uint32_t)(6 - i));
@@ -1395,7 +1416,7 @@ int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
     Lat3 a = st->la;
     for (int64_t i = 0; i < nsteps; ++i) {
         t_begin(st, CVF3_K_VOLUME, s);
-        vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolMet);
+        vol3_kernel<<<1, 64, 0, s>>>(a, kVolMet);
         t_end(st, CVF3_K_VOLUME, s);
         t_begin(st, CVF3_K_ETA, s);
         if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
@@ -1422,7 +1443,7 @@ int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
     const Lat3& a = st->la;
     for (int64_t i = 0; i < nsteps; ++i) {
         t_begin(st, CVF3_K_VOLUME, s);
-        vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolSw);
+        vol3_kernel<<<1, 64, 0, s>>>(a, kVolSw);
         t_end(st, CVF3_K_VOLUME, s);
         t_begin(st, CVF3_K_ETA, s);
         if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
@@ -1475,7 +1496,7 @@ int cvf3_observables(cvf3_state* st, cvf3_obs* out, void* stream)
     if (!st || !out) return CVF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Lat3& a = st->la;
-    vol3_kernel<<<1, kBlock, 0, s>>>(a, kVolFold);
+    vol3_kernel<<<1, 64, 0, s>>>(a, kVolFold);
     zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
     recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
     int rc = hs(hipGetLastError());
