@@ -12,6 +12,10 @@
 //                 of that arm moves once (the arm-domain partition of
 //                 Sec. II.C); a lane moves two x-adjacent cells, which share
 //                 one Philox block
+// A Swendsen-Wang step (Sec. II.D) replaces the passes by sw3_bonds_kernel
+// (link masks, cooperative links closed in registers), sw3_tile_union_kernel
+// (in-tile covalent links, LDS union-find), sw3_union_kernel (tile-crossing
+// links, global union-find), sw3_flip_kernel (cluster shifts) and a recount.
 // Layout: sigma[a*N + c], eta[d*N + c] (edge from c to its +d neighbour),
 // c = x + L*(y + L*z); arms 0:+x 1:-x 2:+y 3:-y 4:+z 5:-z.
 #include <hip/hip_runtime.h>
@@ -41,7 +45,7 @@ struct Dev3State {
     int64_t t_next, t_cur;
     int64_t n_hb_raw, n_coop;
     int64_t met_att, met_acc, eta_att, eta_acc, vol_att, vol_acc;
-    int32_t theta, fold_only;
+    int32_t theta, pad0;
     int32_t order[6];
     int32_t pad[2];
 };
