@@ -122,7 +122,7 @@ ALU_OPS_3D = 39      # half a Philox block (20) + decision over five other arms 
 BYTES_3D = 9         # six own bond indices + facing one + the edge's eta read, one written
 
 
-def bench_cvf3(torch, W, K, L=260):
+def bench_cvf3(torch, W, K, L=260, with_autocorr=True):
     """The paper's own model and size: cubic lattice with eta, N = 260^3, one
     step = volume move + eta moves + six arm-domain passes (Sec. II.B-C)."""
     from paper_2505_05919_amd import cvf, cvf3
@@ -155,7 +155,27 @@ def bench_cvf3(torch, W, K, L=260):
                               "alu": {"achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                                       "frac": round(tops / VALU_PEAK_TOPS, 4), "ops_per_update": ALU_OPS_3D}},
             "paper_rtx3060_ms_per_step": 280.0,
-            "sw": bench_cvf3_sw(torch, W, max(K // 2, 10))}
+            "sw": bench_cvf3_sw(torch, W, max(K // 2, 10)),
+            "autocorr": bench_cvf3_autocorr(torch) if with_autocorr else None}
+
+
+def bench_cvf3_autocorr(torch, L=32):
+    """Sec. III.A / III.C in the paper's own model and size (N = 32^3 =
+    32 768): tau of the order parameter and the cost of an independent
+    configuration for the arm-domain Metropolis and for Swendsen-Wang at the
+    three state points of its Metropolis/SW comparison."""
+    from paper_2505_05919_amd import autocorr, cvf, cvf3
+    pts = []
+    for T, P in ((205.0, -300.0), (205.0, 0.1), (195.0, 160.0)):
+        met = autocorr.measure3(cvf, cvf3, torch, L, T, P, 31, "met", warm=5000, n_rec=20000)
+        sw = autocorr.measure3(cvf, cvf3, torch, L, T, P, 31, "sw", warm=1000, n_rec=4000)
+        cheaper = None
+        if met["cost_per_independent_us"] and sw["cost_per_independent_us"]:
+            cheaper = "sw" if sw["cost_per_independent_us"] < met["cost_per_independent_us"] else "met"
+        elif sw["cost_per_independent_us"]:
+            cheaper = "sw"
+        pts.append({"T_K": T, "P_MPa": P, "met": met, "sw": sw, "cheaper": cheaper})
+    return {"L": L, "N": L ** 3, "max_lag": 2000, "points": pts}
 
 
 def bench_cvf3_sw(torch, W, K, L=128):
@@ -460,7 +480,7 @@ def main():
     c3 = None
     if not args.skip_cvf3:
         log(f"cubic lattice with eta: L=260, warmup {min(W, 20)}, steps {args.cvf3_steps}")
-        c3 = bench_cvf3(torch, min(W, 20), args.cvf3_steps)
+        c3 = bench_cvf3(torch, min(W, 20), args.cvf3_steps, with_autocorr=not args.skip_autocorr)
         log(f"cvf3: {c3}")
 
     # ---------------- autocorrelation and cost per independent configuration ----------------

@@ -108,6 +108,12 @@ int cvf3_sw_steps(cvf3_state *st, int64_t nsteps, void *stream);
  * step or without CVF_ALGO_SW. */
 int cvf3_labels(cvf3_state *st, uint32_t *d_out, void *stream);
 
+/* Adds N_q' (q' = 0..5) of the current sigma into d_counts[0..5] (device,
+ * int64, 8-byte aligned; the caller zeroes it), without synchronising: one
+ * call per step records the order parameter M(t) = max_q' N_q' / (6N) of
+ * Sec. III.A on the device.  CVF_EINVAL for NULL or misaligned pointers. */
+int cvf3_state_counts(cvf3_state *st, int64_t *d_counts, void *stream);
+
 /* Observables of the current state from a full recount, with the chain's
  * counters; `consistent` compares the incrementally kept N_HB_raw, N_sigma
  * with the recount.  Synchronises the stream. */

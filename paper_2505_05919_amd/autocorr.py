@@ -52,6 +52,14 @@ def tau_1e(C) -> float:
     return float("nan")
 
 
+def resolvable(C) -> bool:
+    """False when the series is too nearly constant for the estimator: a
+    stationary series has |C_M(1)| <= 1, and values above it come only from
+    the finite-series terms of c_m (the lagged mean runs over T - dt points),
+    which dominate when the variance of M is below about <M>^2 / T."""
+    return abs(float(C[1])) <= 1.0
+
+
 def record_counts(cvf, chain, step, nsteps: int):
     """Run nsteps steps of chain with step(n) (e.g. chain.metropolis) and
     return the [nsteps, 6] state counts after each step (one device read)."""
@@ -77,7 +85,7 @@ def measure(cvf, torch, L: int, T: float, P: float, seed: int, algo: str, warm: 
     step(warm)
     counts = record_counts(cvf, ch, step, n_rec)
     C = c_m(order_parameter(counts, 4 * L * L), min(max_lag, n_rec // 2))
-    tau = tau_1e(C)
+    tau = tau_1e(C) if resolvable(C) else float("nan")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step(n_time)
@@ -90,3 +98,43 @@ def measure(cvf, torch, L: int, T: float, P: float, seed: int, algo: str, warm: 
             "C_M_1": round(float(C[1]), 4), "step_us": round(t_step * 1e6, 2),
             "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None,
             "consistent": consistent}
+
+
+def record_counts3(cvf3, chain, step, nsteps: int):
+    """The cubic-lattice chain's [nsteps, 6] state counts after each of
+    nsteps steps of step(n) (chain.steps or chain.sw), one device read."""
+    import torch
+    out = torch.zeros((nsteps, 6), dtype=torch.int64, device=chain.sigma.device)
+    base = out.data_ptr()
+    for i in range(nsteps):
+        step(1)
+        cvf3.cvf3_state_counts(chain.h, base + 48 * i, chain.stream)
+    return out.cpu().numpy()
+
+
+def measure3(cvf, cvf3, torch, L: int, T: float, P: float, seed: int, algo: str, warm: int, n_rec: int,
+             n_time: int = 2000, max_lag: int = 2000) -> dict:
+    """measure() for the cubic lattice with eta (the paper's own model, Sec.
+    III.A and III.C): arm-domain Metropolis ("met") or Swendsen-Wang ("sw")
+    steps, M normalised by the 6N bond indices."""
+    p = cvf.cvf_params_from_si(T, P, L=L, seed=seed)
+    ch = cvf3.Chain3(p, algo_mask=cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+    step = ch.steps if algo == "met" else ch.sw
+    step(warm)
+    counts = record_counts3(cvf3, ch, step, n_rec)
+    M = order_parameter(counts, 6 * L ** 3)
+    C = c_m(M, min(max_lag, n_rec // 2))
+    tau = tau_1e(C) if resolvable(C) else float("nan")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(n_time)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / n_time
+    o = ch.obs()
+    ch.close()
+    ok = not math.isnan(tau)
+    return {"warmup_steps": warm, "steps_recorded": n_rec, "tau_steps": round(float(tau), 3) if ok else None,
+            "C_M_1": round(float(C[1]), 4), "step_us": round(t_step * 1e6, 2),
+            "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None,
+            "v": round(o["v"], 4), "M_mean": round(float(M.mean()), 4), "M_std": float("%.3g" % M.std()),
+            "resolvable": resolvable(C), "consistent": o["consistent"] == 1}

@@ -1110,6 +1110,33 @@ __global__ __launch_bounds__(kBlock) void recount3_kernel(Lat3 a)
     block_slots<9>(v, a.rc);
 }
 
+// N_q' of the current sigma added to out[0..5]: the 6N bytes read as 32-bit
+// words; the bytes of w equal to k are the zero bytes of w ^ k 0x01010101,
+// counted exactly (no carry crosses a byte) with one popcount.
+__global__ __launch_bounds__(kBlock) void counts3_kernel(const uint32_t* __restrict__ words, uint32_t nwords,
+                                                         int64_t* out)
+{
+    int c[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nwords; i += gridDim.x * kBlock) {
+        const uint32_t w = words[i];
+#pragma unroll
+        for (uint32_t k = 0; k < 6; ++k) c[k] += __popc(zero_bytes(w ^ (k * 0x01010101u)));
+    }
+    __shared__ int part[6][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sm = wave_sum(c[k]);
+        if (lane == 0) part[k][wv] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int64_t sm = 0;
+        for (int i = 0; i < kBlock / 64; ++i) sm += part[threadIdx.x][i];
+        if (sm) atomicAdd((unsigned long long*)(out + threadIdx.x), (unsigned long long)sm);
+    }
+}
+
 __global__ void zero_kernel(int64_t* p, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -1493,6 +1520,17 @@ int cvf3_labels(cvf3_state* st, uint32_t* d_out, void* stream)
     if (rc == CVF_OK)
         rc = hs(hipMemcpyAsync(d_out, a.par, 6ull * a.N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     return rc;
+}
+
+int cvf3_state_counts(cvf3_state* st, int64_t* d_counts, void* stream)
+{
+    if (!st || !d_counts || ((uintptr_t)d_counts & 7)) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t nwords = (uint32_t)(6ull * st->la.N / 4);
+    uint64_t blocks = (nwords + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    counts3_kernel<<<(unsigned)blocks, kBlock, 0, s>>>((const uint32_t*)st->sigma, nwords, d_counts);
+    return hs(hipGetLastError());
 }
 
 int cvf3_observables(cvf3_state* st, cvf3_obs* out, void* stream)

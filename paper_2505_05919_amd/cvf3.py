@@ -17,7 +17,7 @@ CVF3_MAX_L = 1290
  CVF3_K_COUNT) = range(7)
 
 EXPORTS = ["cvf3_workspace_bytes", "cvf3_tables", "cvf3_init", "cvf3_steps", "cvf3_sw_steps", "cvf3_labels",
-           "cvf3_observables", "cvf3_timing_enable", "cvf3_kernel_times", "cvf3_destroy"]
+           "cvf3_state_counts", "cvf3_observables", "cvf3_timing_enable", "cvf3_kernel_times", "cvf3_destroy"]
 
 
 class cvf3_obs(ctypes.Structure):
@@ -50,6 +50,7 @@ def lib():
         L.cvf3_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf3_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf3_labels.argtypes = [vp, vp, vp]
+        L.cvf3_state_counts.argtypes = [vp, vp, vp]
         L.cvf3_observables.argtypes = [vp, ctypes.POINTER(cvf3_obs), vp]
         L.cvf3_timing_enable.argtypes = [vp, ctypes.c_int]
         L.cvf3_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
@@ -103,6 +104,11 @@ def cvf3_labels(h, out, stream=None):
     op, _ = _devptr(out, "torch.int32", out.numel() * 4)
     _check("cvf3_labels", lib().cvf3_labels(h, op, _stream(stream)))
     return out
+
+
+def cvf3_state_counts(h, d_counts: int, stream=None):
+    """Add N_q' of the current sigma into the 6 int64 at device address d_counts."""
+    _check("cvf3_state_counts", lib().cvf3_state_counts(h, ctypes.c_void_p(d_counts), _stream(stream)))
 
 
 def cvf3_observables(h, stream=None) -> dict:

@@ -94,6 +94,7 @@ def test_null_pointers_rejected(c3):
     assert L.cvf3_steps(None, 1, None) == cvf.CVF_EINVAL
     assert L.cvf3_sw_steps(None, 1, None) == cvf.CVF_EINVAL
     assert L.cvf3_labels(None, None, None) == cvf.CVF_EINVAL
+    assert L.cvf3_state_counts(None, None, None) == cvf.CVF_EINVAL
     assert L.cvf3_observables(None, None, None) == cvf.CVF_EINVAL
     assert L.cvf3_destroy(None) == cvf.CVF_EINVAL
     assert L.cvf3_workspace_bytes(ctypes.byref(p), 1, None) == cvf.CVF_EINVAL

@@ -54,3 +54,18 @@ def test_order_parameter_and_errors():
         autocorr.c_m([1.0, 1.0, 1.0], 1)
     with pytest.raises(ValueError):
         autocorr.c_m([1.0, 2.0], 2)
+
+
+def test_nearly_constant_series_is_not_resolvable():
+    """M(t) that only jitters at the last digits (as under cluster shifts of
+    an ordered lattice, which permute the state counts) gives C_M(1) > 1,
+    impossible for a stationary series: tau is then reported undefined."""
+    import numpy as np
+    from paper_2505_05919_amd import autocorr
+    rng = np.random.default_rng(3)
+    x = 0.99 + 1e-7 * rng.standard_normal(4000)
+    x[0] = x[-1] = 0.99 + 3e-7                      # the end terms of the lagged mean dominate the variance
+    C = autocorr.c_m(x, 10)
+    assert not autocorr.resolvable(C)
+    y = np.sin(np.arange(4000) / 50.0) + 0.1 * rng.standard_normal(4000)
+    assert autocorr.resolvable(autocorr.c_m(y, 10))

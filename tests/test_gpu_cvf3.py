@@ -211,3 +211,21 @@ def test_cvf3_sw_state_errors(c3, oracle_mod):
         ch.labels()                                          # before the first SW step
     assert e.value.code == cvf.CVF_ESTATE
     ch.close()
+
+
+@pytest.mark.parametrize("algo", ["met", "sw"])
+def test_cvf3_state_counts_series(c3, oracle_mod, algo):
+    """The per-step N_q' series recorded on the device (the order parameter
+    of Sec. III.A) equals the oracle's counts after every step."""
+    from oracle import cvf3 as o3
+    from paper_2505_05919_amd import autocorr, cvf
+    op = oracle_mod.params_from_si(220.0, 0.1, L=6, seed=77)
+    ch = c3.Chain3(gpu_params(cvf, op), algo_mask=cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+    oc = o3.Chain3(op)
+    got = autocorr.record_counts3(c3, ch, ch.steps if algo == "met" else ch.sw, 40)
+    want = []
+    for _ in range(40):
+        (oc.steps if algo == "met" else oc.sw)(1)
+        want.append(oc.obs()["count"])
+    assert np.array_equal(got, np.asarray(want, dtype=np.int64))
+    ch.close()
