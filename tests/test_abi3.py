@@ -98,3 +98,22 @@ def test_null_pointers_rejected(c3):
     assert L.cvf3_observables(None, None, None) == cvf.CVF_EINVAL
     assert L.cvf3_destroy(None) == cvf.CVF_EINVAL
     assert L.cvf3_workspace_bytes(ctypes.byref(p), 1, None) == cvf.CVF_EINVAL
+
+
+def test_init_rejects_misaligned_and_short_arguments(c3):
+    """cvf3_init validates before any device call: misaligned lattice or
+    workspace pointers and a short workspace come back as errors."""
+    import ctypes
+    from paper_2505_05919_amd import cvf
+    p = _p(c3, L=8)
+    need = c3.cvf3_workspace_bytes(p)
+    L = c3.lib()
+    h = ctypes.c_void_p()
+    ok, odd = ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 2)
+    assert L.cvf3_init(ctypes.byref(p), 1, odd, ok, ok, need, None, ctypes.byref(h)) == cvf.CVF_EINVAL
+    assert L.cvf3_init(ctypes.byref(p), 1, ok, odd, ok, need, None, ctypes.byref(h)) == cvf.CVF_EINVAL
+    assert L.cvf3_init(ctypes.byref(p), 1, ok, ok, ctypes.c_void_p((1 << 20) + 64), need, None,
+                       ctypes.byref(h)) == cvf.CVF_EINVAL
+    assert L.cvf3_init(ctypes.byref(p), 1, ok, ok, ok, need - 1, None, ctypes.byref(h)) == cvf.CVF_ENOMEM
+    assert L.cvf3_init(ctypes.byref(p), 8, ok, ok, ok, need, None, ctypes.byref(h)) == cvf.CVF_EINVAL
+    assert not h.value
