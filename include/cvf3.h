@@ -14,9 +14,7 @@
  *          tables
  * Both lattice buffers must be 4-byte aligned and the workspace 256-byte
  * aligned; all three must stay valid until cvf3_destroy.  Every call that
- * takes a stream enqueues its kernels there (NULL = the default stream) and
- * returns without waiting, except cvf3_init and cvf3_observables, which
- * synchronise the stream.
+ * takes a stream enqueues its kernels there (NULL = the default stream).
  *
  * One MC step (cvf3_steps), in the paper's order:
  *   1. volume move of v_iso with sigma, eta fixed (Metropolis, FP64);
@@ -30,7 +28,16 @@
  *      with dH = -theta eta J_eff dh - J_sigma dc (dc over the five other
  *      arms of the cell).
  * Random numbers: Philox4x32-10 keyed by the seed, one counter per draw, so
- * a chain's trajectory depends only on (params, seed), not on the launch.
+ * a chain's trajectory depends only on (params, seed) and the sequence of
+ * calls, not on the launch; the step enters the counter as 32 bits, so a
+ * chain runs at most 2^32 steps before its draws repeat.
+ *
+ * Conventions (as in cvf.h): every function returns CVF_OK or a negative
+ * CVF_E* code, validation happens before any device call and leaves the
+ * state unchanged; the library allocates no device memory; cvf3_init,
+ * cvf3_observables and cvf3_kernel_times synchronise the stream, the other
+ * calls are asynchronous on it; a cvf3_state is not thread-safe, distinct
+ * states are independent and may run concurrently on different streams.
  */
 #ifndef CVF3_H
 #define CVF3_H
