@@ -38,7 +38,7 @@ constexpr int kSlots = 256;              // counter slots, spread to avoid one h
 constexpr int kAcc = 4;                  // d N_HB_raw, d N_sigma, sigma accepted, eta accepted
 constexpr int kRc = 10;                  // recount: N_HB_raw, N_sigma, N_q' (6), eta = 0 edges, spare
 constexpr int kBlock = 256;
-constexpr uint32_t kQuadsPerLane = 2;    // quad pass: quads per lane (grid-stride)
+constexpr uint32_t kQuadsPerLane = 4;    // quad pass: quads per lane (grid-stride)
 
 struct Dev3State {
     double  v, u;
@@ -777,15 +777,16 @@ __global__ __launch_bounds__(kBlock) void pass3_kernel(Lat3 a)
         default: pass_pair<5>(a, met, p, t, theta, cnt); break;
         }
     }
-    // The three counters of a lane (d N_HB_raw in [-8, 8], d N_sigma in
-    // [-40, 40], accepted in [0, 8] for two quads) biased and packed into one
-    // word and summed over 16 lanes (sums below 2^9, 2^11, 2^8), then
-    // unpacked and summed over the four 16-lane rows.
-    static_assert(kQuadsPerLane == 2, "field widths below hold for two quads per lane");
-    uint32_t v = (uint32_t)(cnt[1] + 40) | ((uint32_t)(cnt[0] + 8) << 11) | ((uint32_t)cnt[2] << 20);
+    // The three counters of a lane (d N_HB_raw in [-16, 16], d N_sigma in
+    // [-80, 80], accepted in [0, 16] for four quads) biased and packed into
+    // one word and summed over 16 lanes (sums at most 512, 2560 and 256:
+    // fields of 10, 12 and 9 bits), then unpacked and summed over the four
+    // 16-lane rows.
+    static_assert(kQuadsPerLane <= 4, "field widths below hold for up to four quads per lane");
+    uint32_t v = (uint32_t)(cnt[1] + 80) | ((uint32_t)(cnt[0] + 16) << 12) | ((uint32_t)cnt[2] << 22);
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
-    int r3[3] = {(int)((v >> 11) & 0x1FFu) - 16 * 8, (int)(v & 0x7FFu) - 16 * 40, (int)(v >> 20)};
+    int r3[3] = {(int)((v >> 12) & 0x3FFu) - 16 * 16, (int)(v & 0xFFFu) - 16 * 80, (int)(v >> 22)};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         r3[k] += __shfl_xor(r3[k], 16, 64);
