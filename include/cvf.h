@@ -109,10 +109,14 @@ typedef struct cvf_state cvf_state;
  * seed = 1, flags = 0.  Host only.  CVF_EINVAL if out is NULL or T <= 0. */
 int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
 
-/* Device workspace needed for the algorithms in algo_mask: Metropolis
- * needs a few KB; Swendsen-Wang adds 25 bytes per cell (uint32 labels and
- * uint16 tile-local roots of the 4N bond indices, one bond mask byte per
- * cell) and 96 bytes per 64 x 32-cell tile.  Host only. */
+/* Device workspace needed for the algorithms in algo_mask.  Metropolis
+ * (Sec. II.C) needs a few KB: the chain's scalars, counter slots and the
+ * acceptance table.  Swendsen-Wang (Sec. II.D) adds the state of its
+ * labelling -- the paper's bond array and label array of every bond index
+ * -- as 25 bytes per cell (uint32 labels and uint16 tile-local roots of the
+ * 4N bond indices, one bond mask byte per cell) and 96 bytes per 64 x
+ * 32-cell tile.  Host only.  CVF_EINVAL for a NULL argument, invalid
+ * parameters or an empty algo_mask. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
 /* Create a chain.  d_sigma: 4*L*L bytes of device memory (4-byte aligned:
@@ -168,8 +172,10 @@ int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
  * per step of a long run and read the series once.  Asynchronous. */
 int cvf_state_counts(cvf_state *st, int64_t *d_counts, void *stream);
 
-/* Write the cluster labels of the last Swendsen-Wang step (4*L*L uint32,
- * label[idx] = smallest flat index in idx's cluster) to device memory
+/* Write the cluster labels of the last Swendsen-Wang step (Sec. II.D: the
+ * label array of every bond index, converged to the smallest flat index of
+ * its cluster, the fixed point of the worked example in Table II; 4*L*L
+ * uint32, label[idx] = smallest flat index in idx's cluster) to device memory
  * d_out, which must not overlap the chain's workspace or sigma.
  * CVF_ESTATE if no Swendsen-Wang step has run.  Waits for the stream's
  * earlier work (to read that flag), then enqueues the write. */
@@ -182,10 +188,15 @@ int cvf_labels(cvf_state *st, uint32_t *d_out, void *stream);
  * Asynchronous. */
 int cvf_set_stop(cvf_state *st, int64_t stop_at, void *stream);
 
-/* Test hook: the host-computed acceptance tables of this chain.
+/* Test hook: the host-computed acceptance tables of this chain.  They
+ * encode the Metropolis acceptance min(1, exp(-beta dH)) of Sec. II.C with
+ * dH from Eq. (3) (dH = -theta J_eff dN_HB - J_sigma dN_sigma, J_eff =
+ * J - P v_HB), and the Swendsen-Wang bond probabilities 1 - exp(-beta J_sigma)
+ * and 1 - exp(-beta |J_eff|) of Sec. II.D, scaled by 2^32.
  * met[theta][dh+1][dc+3]: accept iff thr == 0xFFFFFFFF or word < thr.
  * sw[0] cooperative bond threshold, sw[1], sw[2] covalent thresholds for
- * theta = 0, 1 (bond iff word < thr, 64-bit compare).  Host only. */
+ * theta = 0, 1 (bond iff word < thr, 64-bit compare).  Host only;
+ * CVF_EINVAL for a NULL argument. */
 int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
 
 /* Kernel timing.  While enabled, every launch of the kernels of one kind

@@ -3,11 +3,16 @@ independent configuration (Sec. III.C), from series the library records on
 the device.
 
 M(t) = max_q' N_q'(t) / n, n the number of bond indices (4N in 2-D);
-C_M(dt) = (<M(t0 + dt) M(t0)> - <M>^2) / (<M^2> - <M>^2), the first mean
-over the t0 with t0 + dt in the series, the others over the whole series;
-tau = the lag at which C_M falls to 1/e (linear interpolation between the
-two integer lags around the crossing); configurations tau steps apart count
-as independent, so one costs tau times the wall time of a step.
+C_M(dt) = (<M(t0 + dt) M(t0)> - <M>^2) / (<M^2> - <M>^2) (Eq. (4)),
+estimated from the mean-centred series d(t) = M(t) - <M> as
+<d(t0 + dt) d(t0)> / <d^2>, the first mean over the t0 with t0 + dt in the
+series.  For a stationary series this has the expectation of Eq. (4); the
+uncentred form <M(t0 + dt) M(t0)> - <M>^2 mixes in the difference between
+the means of the two lagged sub-series times <M>, which swamps the variance
+when M barely moves about a large mean (an ordered lattice under cluster
+shifts).  tau = the lag at which C_M falls to 1/e (linear interpolation
+between the two integer lags around the crossing); configurations tau steps
+apart count as independent, so one costs tau times the wall time of a step.
 
 The counts come from cvf_state_counts, one row per step, accumulated on the
 device and read once; the statistics are host arithmetic on that series.
@@ -25,18 +30,19 @@ def order_parameter(counts, n_bond: int) -> np.ndarray:
 
 
 def c_m(M, max_lag: int) -> np.ndarray:
-    """C_M(dt) for dt = 0..max_lag (C_M(0) = 1)."""
+    """C_M(dt) for dt = 0..max_lag (C_M(0) = 1), from the mean-centred
+    lagged products."""
     x = np.asarray(M, dtype=np.float64)
     T = x.size
     if max_lag >= T:
         raise ValueError("max_lag must be below the series length")
-    mean = x.mean()
-    var = (x * x).mean() - mean * mean
+    d = x - x.mean()
+    var = (d * d).mean()
     if not var > 0.0:
         raise ValueError("constant series: C_M is undefined")
     out = np.empty(max_lag + 1)
     for dt in range(max_lag + 1):
-        out[dt] = ((x[dt:] * x[:T - dt]).mean() - mean * mean) / var
+        out[dt] = (d[dt:] * d[:T - dt]).mean() / var
     return out
 
 
@@ -50,14 +56,6 @@ def tau_1e(C) -> float:
             c0, c1 = C[k - 1], C[k]
             return (k - 1) + (c0 - target) / (c0 - c1)
     return float("nan")
-
-
-def resolvable(C) -> bool:
-    """False when the series is too nearly constant for the estimator: a
-    stationary series has |C_M(1)| <= 1, and values above it come only from
-    the finite-series terms of c_m (the lagged mean runs over T - dt points),
-    which dominate when the variance of M is below about <M>^2 / T."""
-    return abs(float(C[1])) <= 1.0
 
 
 def record_counts(cvf, chain, step, nsteps: int):
@@ -85,7 +83,7 @@ def measure(cvf, torch, L: int, T: float, P: float, seed: int, algo: str, warm: 
     step(warm)
     counts = record_counts(cvf, ch, step, n_rec)
     C = c_m(order_parameter(counts, 4 * L * L), min(max_lag, n_rec // 2))
-    tau = tau_1e(C) if resolvable(C) else float("nan")
+    tau = tau_1e(C)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step(n_time)
@@ -124,7 +122,7 @@ def measure3(cvf, cvf3, torch, L: int, T: float, P: float, seed: int, algo: str,
     counts = record_counts3(cvf3, ch, step, n_rec)
     M = order_parameter(counts, 6 * L ** 3)
     C = c_m(M, min(max_lag, n_rec // 2))
-    tau = tau_1e(C) if resolvable(C) else float("nan")
+    tau = tau_1e(C)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step(n_time)
@@ -137,4 +135,4 @@ def measure3(cvf, cvf3, torch, L: int, T: float, P: float, seed: int, algo: str,
             "C_M_1": round(float(C[1]), 4), "step_us": round(t_step * 1e6, 2),
             "cost_per_independent_us": round(float(tau) * t_step * 1e6, 2) if ok else None,
             "v": round(o["v"], 4), "M_mean": round(float(M.mean()), 4), "M_std": float("%.3g" % M.std()),
-            "resolvable": resolvable(C), "consistent": o["consistent"] == 1}
+            "consistent": o["consistent"] == 1}

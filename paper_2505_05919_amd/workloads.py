@@ -79,3 +79,14 @@ def c5_stream(n_jobs: int = 2000, rate: float = 200.0, seed: int = 5,
         algo = "met" if rng.random() < 0.8 else "sw"
         jobs.append(Job(L, T, P, ns, algo, 5000 + n, t))
     return jobs
+
+
+def c5_oracle_subset(jobs: list[Job], n_random: int = 16, seed: int = 5005) -> list[int]:
+    """Indices of the served jobs whose results are checked against stored CPU
+    reference runs: every job with L <= 256, plus n_random of the larger ones
+    drawn uniformly (without replacement) by default_rng(seed)."""
+    small = [n for n, j in enumerate(jobs) if j.L <= 256]
+    rest = [n for n, j in enumerate(jobs) if j.L > 256]
+    rng = np.random.default_rng(seed)
+    extra = rng.choice(len(rest), size=min(n_random, len(rest)), replace=False)
+    return sorted(small + [rest[int(i)] for i in extra])

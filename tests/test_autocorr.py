@@ -11,9 +11,9 @@ from paper_2505_05919_amd import autocorr
 
 
 def test_four_point_series_by_hand():
-    # M = 1, 2, 3, 4: <M> = 5/2, <M^2> = 15/2, variance 5/4;
-    # lag 1: <M(t+1) M(t)> over (2, 6, 12) = 20/3, C = (20/3 - 25/4) / (5/4) = 1/3
-    # lag 2: over (3, 8) = 11/2, C = (11/2 - 25/4) / (5/4) = -3/5
+    # M = 1, 2, 3, 4: <M> = 5/2, d = (-3/2, -1/2, 1/2, 3/2), <d^2> = 5/4;
+    # lag 1: <d(t+1) d(t)> over (3/4, -1/4, 3/4) = 5/12, C = (5/12) / (5/4) = 1/3
+    # lag 2: over (-3/4, -3/4) = -3/4, C = (-3/4) / (5/4) = -3/5
     C = autocorr.c_m([1.0, 2.0, 3.0, 4.0], 2)
     assert C[0] == pytest.approx(1.0, abs=1e-15)
     assert C[1] == pytest.approx(1.0 / 3.0, abs=1e-15)
@@ -56,16 +56,39 @@ def test_order_parameter_and_errors():
         autocorr.c_m([1.0, 2.0], 2)
 
 
-def test_nearly_constant_series_is_not_resolvable():
-    """M(t) that only jitters at the last digits (as under cluster shifts of
-    an ordered lattice, which permute the state counts) gives C_M(1) > 1,
-    impossible for a stationary series: tau is then reported undefined."""
-    import numpy as np
-    from paper_2505_05919_amd import autocorr
-    rng = np.random.default_rng(3)
-    x = 0.99 + 1e-7 * rng.standard_normal(4000)
-    x[0] = x[-1] = 0.99 + 3e-7                      # the end terms of the lagged mean dominate the variance
+def test_uneven_series_by_hand():
+    # M = 1, 1, 2, 4: <M> = 2, d = M - <M> = (-1, -1, 0, 2), <d^2> = 6/4;
+    # lag 1: <d(t+1) d(t)> over (1, 0, 0) = 1/3, C = (1/3) / (3/2) = 2/9.
+    # (The uncentred <M(t+1) M(t)> - <M>^2 = 11/3 - 4 gives -2/9 here.)
+    # lag 3: d(3) d(0) = -2, C = -2 / (3/2) = -4/3
+    C = autocorr.c_m([1.0, 1.0, 2.0, 4.0], 3)
+    assert C[1] == pytest.approx(2.0 / 9.0, abs=1e-15)
+    assert C[3] == pytest.approx(-4.0 / 3.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_independent_series_with_large_mean(seed):
+    """An independent series with the statistics of M under cluster shifts of
+    an ordered lattice (mean 0.99, spread 2.4e-4, 4000 steps) has C_M(dt) = 0
+    for dt > 0; the estimate must scatter by about 1/sqrt(T), not by the
+    ratio of <M>^2 to the variance."""
+    rng = np.random.default_rng(seed)
+    x = 0.9898 + 2.4e-4 * rng.standard_normal(4000)
+    C = autocorr.c_m(x, 20)
+    assert np.all(np.abs(C[1:]) < 5.0 / math.sqrt(4000))
+    assert autocorr.tau_1e(C) < 1.0
+
+
+def test_ar1_with_large_offset_and_tiny_variance():
+    phi, T = 0.8, 200_000
+    rng = np.random.default_rng(12)
+    e = rng.standard_normal(T)
+    x = np.empty(T)
+    x[0] = e[0] / math.sqrt(1 - phi * phi)
+    for t in range(1, T):
+        x[t] = phi * x[t - 1] + e[t]
+    x = 0.99 + 2e-4 * x
     C = autocorr.c_m(x, 10)
-    assert not autocorr.resolvable(C)
-    y = np.sin(np.arange(4000) / 50.0) + 0.1 * rng.standard_normal(4000)
-    assert autocorr.resolvable(autocorr.c_m(y, 10))
+    for dt in (1, 2, 5):
+        assert abs(C[dt] - phi ** dt) < 5 * math.sqrt((1 + phi * phi) / (1 - phi * phi) / T), dt
+    assert autocorr.tau_1e(C) == pytest.approx(-1.0 / math.log(phi), rel=0.03)
