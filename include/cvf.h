@@ -159,6 +159,25 @@ int cvf_metropolis_domain_sweeps(cvf_state *st, int64_t nsweeps, void *stream);
  * J_sigma >= 0 and even L (CVF_EINVAL otherwise).  Asynchronous. */
 int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): a fresh
+ * chain (as cvf_init with these parameters over d_sigma), nsteps
+ * Swendsen-Wang MC steps (as cvf_sw_steps), and its observables in *out (as
+ * cvf_observables) -- the same results as that sequence, bit for bit.  No
+ * caller workspace: the chain's scalars, counter slots, tables, labels, bond
+ * masks and tile roots live in a fixed device array inside the library
+ * (about 6.3 MB on every GPU it runs on, held until the process ends), so
+ * L <= 512; CVF_ENOMEM for a larger L.  The call allocates nothing (no
+ * hipMalloc/hipFree, no host allocation).  d_sigma: 4*L*L bytes of device
+ * memory, 4-byte aligned, filled from Philox stream INIT unless
+ * CVF_KEEP_SIGMA.  CVF_EINVAL for invalid parameters, odd L, J_sigma < 0,
+ * nsteps < 0 or a NULL pointer (all checked before any device call).  Every
+ * call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents (each call re-initialises what it reads): calls that overlap on
+ * one device, on any streams or threads, race and must not be issued.
+ * Synchronises stream. */
+int cvf_sw_steps_noalloc(const cvf_params *p, uint8_t *d_sigma, int64_t nsteps, cvf_obs *out, void *stream);
+
 /* Recount the lattice, evaluate Eq. (1) and (3), and copy everything to
  * *out.  Synchronises stream. */
 int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);

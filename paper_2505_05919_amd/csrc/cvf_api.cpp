@@ -55,14 +55,9 @@ int validate(const cvf_params* p)
     return CVF_OK;
 }
 
-// SW workspace: labels (4N uint32), bond mask (N bytes), tile edge bytes,
-// tile-local roots (4N uint16).
-size_t sw_tiles(uint64_t L) { return ((L + kTW - 1) / kTW) * ((L + kTH - 1) / kTH); }
-size_t sw_bytes(uint64_t L)
-{
-    return align256(4 * L * L * sizeof(uint32_t)) + align256(L * L) + align256(sw_tiles(L) * kEdgeBytes) +
-           align256(4 * L * L * sizeof(uint16_t));
-}
+// SW workspace (labels, bond mask, tile edge bytes, tile-local roots).
+size_t sw_tiles(uint64_t L) { return sw_tiles_of(L); }
+size_t sw_bytes(uint64_t L) { return sw_bytes_of(L); }
 
 // Number of integer points on the circle i^2 + j^2 = m, counted over the
 // first quadrant (i > 0, j >= 0) and multiplied by the 4 rotations.
@@ -190,20 +185,17 @@ int cvf_workspace_bytes(const cvf_params* p, int algo_mask, size_t* bytes)
     return CVF_OK;
 }
 
-int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_bytes, void* stream,
-             cvf_state** out)
+}  // extern "C"
+
+namespace {
+
+// Host fields of a chain over sigma and the workspace at `work` (no device
+// call, no allocation).
+void chain_setup(const cvf_params* p, uint8_t* d_sigma, char* work, size_t work_bytes, cvf_state* st)
 {
-    if (!out || !d_sigma || !d_work) return CVF_EINVAL;
-    int rc = validate(p);
-    if (rc) return rc;
-    if (((uintptr_t)d_work & 255) != 0 || ((uintptr_t)d_sigma & 3) != 0) return CVF_EINVAL;
-    if (work_bytes < kBaseBytes) return CVF_ENOMEM;
-    cvf_state* st = new (std::nothrow) cvf_state();
-    if (!st) return CVF_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     st->p = *p;
     st->sigma = d_sigma;
-    st->work = (char*)d_work;
+    st->work = work;
     st->work_bytes = work_bytes;
     st->N = (uint32_t)p->L * (uint32_t)p->L;
     st->has_sw = work_bytes >= kBaseBytes + sw_bytes((uint64_t)p->L);
@@ -261,12 +253,37 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     v.met_att_add = 0;
     v.mode = kVolMet;
     v.do_volume = (p->flags & CVF_NO_VOLUME_MOVE) ? 0 : 1;
+}
 
-    hipError_t e = hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, st->dtab, p->v_init, s);
-    if (e == hipSuccess && !(p->flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(a, s);
-    if (e == hipSuccess) e = launch_recount(a, st->slots, kSlots, 0, 0, s);
-    if (e != hipSuccess) {
+// Device side of a new chain: tables (copied from the host state, or written
+// by a kernel when the caller may not copy), scalars and counter slots, the
+// initial sigma, the full count.
+hipError_t chain_start(cvf_state* st, bool tables_by_kernel, hipStream_t s)
+{
+    hipError_t e = tables_by_kernel ? launch_tables_init(st->dtab, st->htab, s)
+                                    : hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, st->dtab, st->p.v_init, s);
+    if (e == hipSuccess && !(st->p.flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(st->la, s);
+    if (e == hipSuccess) e = launch_recount(st->la, st->slots, kSlots, 0, 0, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_bytes, void* stream,
+             cvf_state** out)
+{
+    if (!out || !d_sigma || !d_work) return CVF_EINVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (((uintptr_t)d_work & 255) != 0 || ((uintptr_t)d_sigma & 3) != 0) return CVF_EINVAL;
+    if (work_bytes < kBaseBytes) return CVF_ENOMEM;
+    cvf_state* st = new (std::nothrow) cvf_state();
+    if (!st) return CVF_EINVAL;
+    chain_setup(p, d_sigma, (char*)d_work, work_bytes, st);
+    if (chain_start(st, false, (hipStream_t)stream) != hipSuccess) {
         delete st;
         return CVF_EHIP;
     }
@@ -318,6 +335,28 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
         TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, s));
     }
     return CVF_OK;
+}
+
+int cvf_observables(cvf_state* st, cvf_obs* out, void* stream);
+
+int cvf_sw_steps_noalloc(const cvf_params* p, uint8_t* d_sigma, int64_t nsteps, cvf_obs* out, void* stream)
+{
+    // every check that can fail comes before the first device call
+    if (!d_sigma || !out || nsteps < 0) return CVF_EINVAL;
+    int rc = validate(p);
+    if (rc) return rc;
+    if ((p->L & 1) || !(p->Jsigma >= 0.0) || ((uintptr_t)d_sigma & 3) != 0) return CVF_EINVAL;
+    if ((uint32_t)p->L > kNoAllocMaxL) return CVF_ENOMEM;
+    static_assert(kNoAllocBytes >= kBaseBytes + sw_bytes_of(kNoAllocMaxL), "scratch too small");
+    void* scr = nullptr;
+    if (noalloc_scratch(&scr) != hipSuccess) return CVF_EHIP;
+    cvf_state st = cvf_state();          // host state on the stack; timing off, so nothing is allocated
+    chain_setup(p, d_sigma, (char*)scr, kNoAllocBytes, &st);
+    hipStream_t s = (hipStream_t)stream;
+    if (chain_start(&st, true, s) != hipSuccess) return CVF_EHIP;
+    rc = cvf_sw_steps(&st, nsteps, stream);
+    if (rc) return rc;
+    return cvf_observables(&st, out, stream);
 }
 
 int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)

@@ -68,6 +68,21 @@ constexpr size_t kOffTables = kOffSlots + 3 * kSlots * sizeof(int64_t);   // 640
 constexpr size_t kOffObs = kOffTables + 768;                                // 7168
 constexpr size_t kBaseBytes = kOffObs + 512;                                // 7680
 
+// Swendsen-Wang part of a workspace: labels (4N uint32), bond mask (N bytes),
+// per-tile edge bytes, tile-local roots (4N uint16), each 256-aligned.
+constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t sw_tiles_of(uint64_t L) { return ((L + kTW - 1) / kTW) * ((L + kTH - 1) / kTH); }
+constexpr size_t sw_bytes_of(uint64_t L)
+{
+    return align256c(4 * L * L * sizeof(uint32_t)) + align256c(L * L) + align256c(sw_tiles_of(L) * kEdgeBytes) +
+           align256c(4 * L * L * sizeof(uint16_t));
+}
+
+// The allocation-free entry point keeps a whole Swendsen-Wang workspace for
+// lattices up to kNoAllocMaxL in one fixed device array.
+constexpr uint32_t kNoAllocMaxL = 512;
+constexpr size_t kNoAllocBytes = kBaseBytes + sw_bytes_of(kNoAllocMaxL);
+
 static_assert(sizeof(DevState) <= 256, "DevState");
 static_assert(sizeof(DevTables) <= 768, "DevTables");
 static_assert(sizeof(DevObs) <= 512, "DevObs");
@@ -121,6 +136,11 @@ struct BatchEntry {
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
 hipError_t launch_state_init(DevState* st, int64_t* slots, const DevTables* tab, double v_init, hipStream_t s);
 hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s);
+// The tables written by a kernel (argument by value) instead of a copy.
+hipError_t launch_tables_init(DevTables* dst, const DevTables& src, hipStream_t s);
+// Device address of the library's fixed scratch array on the current device
+// (kNoAllocBytes bytes, 256-aligned), looked up once per device.
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);

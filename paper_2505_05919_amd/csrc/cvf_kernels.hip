@@ -6,7 +6,17 @@
 // volume kernel is the only floating-point code (FP64, no contraction).
 #include "cvf_internal.h"
 
+#include <atomic>
+
 namespace cvf {
+
+// Fixed device workspace of the allocation-free entry point
+// (cvf_sw_steps_noalloc): every GPU the library runs on holds one copy,
+// from module load until the process ends.  Host code never passes this
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol); it uses the device address from noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 constexpr int kBlock = 256;           // 4 wavefronts of 64
@@ -363,6 +373,40 @@ hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
 __global__ void set_stop_kernel(DevState* st, int64_t stop_at)
 {
     if (threadIdx.x == 0) st->stop_at = stop_at;
+}
+
+__global__ void tables_init_kernel(DevTables* dst, DevTables src)
+{
+    const uint32_t* in = (const uint32_t*)&src;
+    uint32_t* out = (uint32_t*)dst;
+    for (uint32_t i = threadIdx.x; i < sizeof(DevTables) / 4; i += blockDim.x) out[i] = in[i];
+}
+
+hipError_t launch_tables_init(DevTables* dst, const DevTables& src, hipStream_t s)
+{
+    tables_init_kernel<<<1, 64, 0, s>>>(dst, src);
+    return hipGetLastError();
+}
+
+// Per-device address of `scratch`, taken once per device with that device
+// current (each GPU holds its own copy at its own address).
+hipError_t noalloc_scratch(void** ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::atomic<void*> addr[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void* p = addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidSymbol;
+        addr[dev].store(p, std::memory_order_release);
+    }
+    *ptr = p;
+    return hipSuccess;
 }
 
 hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)

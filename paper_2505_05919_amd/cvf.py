@@ -25,7 +25,7 @@ EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropo
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
            "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_set_stop", "cvf_batch_desc_bytes", "cvf_batch_create",
            "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
-           "cvf_batch_destroy"]
+           "cvf_batch_destroy", "cvf_sw_steps_noalloc"]
 
 
 class CvfError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
         L.cvf_batch_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_batch_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
         L.cvf_batch_destroy.argtypes = [vp]
+        L.cvf_sw_steps_noalloc.argtypes = [P, vp, ctypes.c_int64, ctypes.POINTER(cvf_obs), vp]
         L.cvf_strerror.argtypes = [ctypes.c_int]
         L.cvf_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -169,6 +170,17 @@ def cvf_state_counts(st, d_counts, stream=None):
 
 def cvf_sw_steps(st, nsteps: int, stream=None):
     _check("cvf_sw_steps", lib().cvf_sw_steps(st, nsteps, _stream(stream)))
+
+
+def cvf_sw_steps_noalloc(p: cvf_params, sigma, nsteps: int, stream=None) -> dict:
+    """A fresh chain over sigma (uint8 GPU tensor of 4 L^2 bytes), nsteps
+    Swendsen-Wang steps and its observables, with the library's fixed
+    scratch array as workspace (L <= 512); synchronises the stream."""
+    sp, _ = _devptr(sigma, "torch.uint8", 4 * p.L * p.L)
+    o = cvf_obs()
+    _check("cvf_sw_steps_noalloc",
+           lib().cvf_sw_steps_noalloc(ctypes.byref(p), sp, nsteps, ctypes.byref(o), _stream(stream)))
+    return o.as_dict()
 
 
 def cvf_observables(st, stream=None) -> dict:

@@ -108,3 +108,23 @@ def test_struct_layouts_match_header(cvf):
     # cvf_params: 2 int32 + 7 double + uint64 + 2 uint32 = 80 bytes; cvf_obs: 14 int64 + 4 double + 2 int32
     assert ctypes.sizeof(cvf.cvf_params) == 80
     assert ctypes.sizeof(cvf.cvf_obs) == 14 * 8 + 4 * 8 + 8
+
+
+def test_noalloc_entry_rejects_before_any_device_call(cvf):
+    """cvf_sw_steps_noalloc checks its arguments and the size limit of its
+    fixed scratch array (L <= 512) before touching the device, so the
+    errors come back on a host without a GPU too."""
+    import ctypes
+    lib = cvf.lib()
+    fake = ctypes.c_void_p(1 << 20)                  # aligned, never dereferenced
+    o = cvf.cvf_obs()
+    big = cvf.cvf_params_from_si(300.0, 0.1, L=514)
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(big), fake, 1, ctypes.byref(o), None) == cvf.CVF_ENOMEM
+    odd = cvf.cvf_params_from_si(300.0, 0.1, L=63)
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(odd), fake, 1, ctypes.byref(o), None) == cvf.CVF_EINVAL
+    ok = cvf.cvf_params_from_si(300.0, 0.1, L=64)
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(ok), None, 1, ctypes.byref(o), None) == cvf.CVF_EINVAL
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(ok), fake, -1, ctypes.byref(o), None) == cvf.CVF_EINVAL
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(ok), fake, 1, None, None) == cvf.CVF_EINVAL
+    neg = cvf.cvf_params_from_si(300.0, 0.1, L=64, Jsigma=-0.1)
+    assert lib.cvf_sw_steps_noalloc(ctypes.byref(neg), fake, 1, ctypes.byref(o), None) == cvf.CVF_EINVAL
