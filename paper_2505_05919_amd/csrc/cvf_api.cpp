@@ -41,6 +41,9 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Rows per lane of a batched Metropolis pass before the autotuner runs.
+constexpr uint32_t kBatchDefaultRows = 8;
+
 int validate(const cvf_params* p)
 {
     if (!p) return CVF_EINVAL;
@@ -237,6 +240,10 @@ void chain_setup(const cvf_params* p, uint8_t* d_sigma, char* work, size_t work_
         a.rows = m.rows;
         a.row_blocks = m.row_blocks;
     }
+    a.met_le = 1;                        // every threshold >= 1: acceptance is word <= thr - 1
+    for (int th = 0; th < 2; ++th)
+        for (int i = 0; i < 21; ++i)
+            if (st->htab.met[th][i] == 0) a.met_le = 0;
 
     VolArgs& v = st->va;
     v.st = st->dst;
@@ -298,10 +305,14 @@ int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
     VolArgs v = st->va;
     v.mode = kVolMet;
     v.met_att_add = 4 * (int64_t)st->N;
+    // Quad lanes: the colour-1 launch of every sweep but the last opens the
+    // next step in its last workgroup, so the volume move is a launch of its
+    // own only once per call.
+    const bool fold = st->la.quad != 0;
     for (int64_t i = 0; i < nsweeps; ++i) {
-        TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 0, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 1, s));
+        if (i == 0 || !fold) TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour_fold(st->la, v, 0, 0, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour_fold(st->la, v, 1, fold && i + 1 < nsweeps, s));
     }
     return CVF_OK;
 }
@@ -328,11 +339,13 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     VolArgs v = st->va;
     v.mode = kVolSw;
+    // the flip launch of every step but the last opens the next step in its
+    // last workgroup: the volume move is a launch of its own once per call
     for (int64_t i = 0; i < nsteps; ++i) {
-        TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        if (i == 0) TIMED(CVF_K_VOLUME, launch_volume(v, s));
         TIMED(CVF_K_SW_BONDS, launch_sw_tiles(st->la, s));
         TIMED(CVF_K_SW_UNION, launch_sw_union_edges(st->la, s));
-        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, s));
+        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, v, i + 1 < nsteps, s));
     }
     return CVF_OK;
 }
@@ -501,25 +514,21 @@ int batch_upload(cvf_batch* b, hipStream_t s)
         BatchEntry& e = b->host[c];
         memset(&e, 0, sizeof(e));
         e.la = st->la;
-        if (e.la.quad == 2) {
-            // column pairs in batches: small lattices get twice the
-            // wavefronts (measured faster on the 256-replica mix)
-            const MetShape m = met_shape_mode(e.la.L, 0);
-            e.la.quad = m.quad;
-            e.la.rows = m.rows;
-            e.la.row_blocks = m.row_blocks;
-        }
-        if (b->rows > 0) {
-            const uint32_t segs = (e.la.L + b->rows - 1) / (uint32_t)b->rows;
-            e.la.rows = (uint32_t)b->rows;
-            e.la.row_blocks = (segs + 3) / 4;
-        }
+        // batched passes: quads for L % 4 == 0, column pairs for L % 4 == 2
+        // (no ragged quads: their body raises the register need of the
+        // batched kernel past its 8-wavefront budget)
+        e.la.quad = (e.la.L % 4 == 0) ? 1u : 0u;
         e.va = st->va;
         e.va.mode = kVolMet;
         e.va.met_att_add = 4 * (int64_t)st->N;
-        const uint32_t per_lane = e.la.quad ? 4 : 2;
-        e.groups_x = ((e.la.L + per_lane - 1) / per_lane + 63) / 64;
-        e.blocks = e.groups_x * e.la.row_blocks;
+        const uint32_t Lc = e.la.L;
+        e.upr = e.la.quad ? Lc / 4 : Lc / 2;
+        e.upr_inv = 1.0 / (double)e.upr;
+        e.units = e.upr * (Lc / 2);
+        // rows per lane (the tuned parameter) = 2 rows per unit
+        const uint32_t rows = b->rows > 0 ? (uint32_t)b->rows : kBatchDefaultRows;
+        e.iters = rows / 2 < 1 ? 1 : rows / 2;
+        e.blocks = (uint32_t)(((uint64_t)e.units + 256ull * e.iters - 1) / (256ull * e.iters));
         b->start[c] = total;
         total += e.blocks;
         const uint32_t L = (uint32_t)st->p.L;

@@ -45,6 +45,8 @@ struct DevState {
     int32_t sw_done;         // a Swendsen-Wang step has produced labels
     int32_t skip;            // 1: the step limit is reached, step kernels do nothing
     int64_t stop_at;         // no step with index >= stop_at is performed
+    uint32_t arrive;         // workgroups of the current colour-1 launch that have finished (wraps to 0)
+    uint32_t pad_;
 };
 
 // Host-computed constants copied to the workspace at init.
@@ -108,6 +110,7 @@ struct LatticeArgs {
     uint32_t rows;           // Metropolis: rows per wavefront (even, <= 32)
     uint32_t row_blocks;     // Metropolis: grid.y
     uint32_t quad;           // Metropolis: 1 / 2 = dword (4-column) lanes, L % 4 == 0 / 2; 0 = column pairs
+    uint32_t met_le;         // 1: no Metropolis threshold is 0, so acceptance is one compare (word <= thr - 1)
 };
 
 struct VolArgs {
@@ -123,14 +126,17 @@ struct VolArgs {
 
 enum VolMode { kVolMet = 0, kVolSw = 1, kVolFold = 2 };
 
-// One chain of a batch: its launch arguments, its own launch shape
-// (groups_x workgroups per row block) and its workgroup count.
+// One chain of a batch: its launch arguments and the work units of a
+// batched Metropolis colour pass (row pair x column quad, or x column pair
+// for L % 4 == 2), `iters` units per lane, `blocks` workgroups.
 struct BatchEntry {
     LatticeArgs la;
     VolArgs va;
-    uint32_t groups_x;
-    uint32_t blocks;
-    uint32_t pad_[2];
+    uint32_t units;          // units per colour pass: (L / 2) * upr
+    uint32_t upr;            // units per row pair: L / 4 quads, or L / 2 column pairs
+    double upr_inv;          // 1 / upr
+    uint32_t iters;          // units per lane
+    uint32_t blocks;         // workgroups of this chain: ceil(units / (256 iters))
 };
 
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
@@ -144,6 +150,9 @@ hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
+// The checkerboard sweep with quad lanes: colour 1 with fold != 0 also opens
+// the next step (counter fold + volume move, `v`) in its last workgroup.
+hipError_t launch_met_colour_fold(const LatticeArgs& a, const VolArgs& v, int colour, int fold, hipStream_t s);
 // Arm-domain sweep: pass 0..3 of the step's drawn arm order (any L >= 2).
 hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s);
 // step_gate: the recount closes an SW step and is skipped with it.
@@ -158,7 +167,8 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
 // cluster shift fused with the recount.  Labels are written out on request.
 hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s);
+// fold != 0: the last workgroup also opens the next step (volume move `v`).
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, const VolArgs& v, int fold, hipStream_t s);
 hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,
 // count+1 prefix sums of workgroups); all chains share q.

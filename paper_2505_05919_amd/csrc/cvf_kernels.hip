@@ -117,6 +117,8 @@ __global__ void state_init_kernel(DevState* st, int64_t* slots, const DevTables*
         st->sw_done = 0;
         st->skip = 0;
         st->stop_at = INT64_MAX;
+        st->arrive = 0;
+        st->pad_ = 0;
     }
 }
 
@@ -144,7 +146,12 @@ __global__ __launch_bounds__(kBlock) void sigma_init_kernel(LatticeArgs a)
 // ---------------------------------------------------------------------------
 // Executed by one full wavefront (lanes 0..63); `term` is 40 doubles of LDS.
 // Every global load is issued before the first store, so the whole move
-// costs one memory round trip.
+// costs one memory round trip.  EXCH: the slots were filled by atomics of
+// the same launch (the last workgroup of a colour pass opens the next step),
+// so they are read and cleared with device-scope atomic exchanges, which see
+// every other workgroup's atomics wherever it ran; otherwise (a launch of its
+// own) plain loads and stores.
+template <bool EXCH = false>
 __device__ void volume_step(const VolArgs& a, double* term)
 {
     const int lane = threadIdx.x & 63;
@@ -153,7 +160,10 @@ __device__ void volume_step(const VolArgs& a, double* term)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int k = 0; k < kSlots / 64; ++k) sl[j][k] = a.slots[j * kSlots + k * 64 + lane];
+        for (int k = 0; k < kSlots / 64; ++k) {
+            int64_t* p = a.slots + j * kSlots + k * 64 + lane;
+            sl[j][k] = EXCH ? (int64_t)atomicExch((unsigned long long*)p, 0ull) : *p;
+        }
     const int64_t t_next = st->t_next, stop_at = st->stop_at;
     const int64_t hb0 = st->n_hb_raw, co0 = st->n_coop, macc0 = st->met_acc, matt0 = st->met_att;
     const int64_t vatt0 = st->vol_att, vacc0 = st->vol_acc;
@@ -167,10 +177,12 @@ __device__ void volume_step(const VolArgs& a, double* term)
         co += sl[1][k];
         ac += sl[2][k];
     }
+    if (!EXCH) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
+            for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
+    }
     const int64_t n_hb = hb0 + wave_sum64(hb);
     const int64_t n_co = co0 + wave_sum64(co);
     const int64_t m_acc = macc0 + wave_sum64(ac);
@@ -332,32 +344,46 @@ hipError_t launch_volume(const VolArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int Q, bool R>
-void launch_quad_r(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
+template <int Q, bool R, bool LE>
+void launch_quad_r(const LatticeArgs& a, const VolArgs& v, int colour, int fold, dim3 grid, hipStream_t s)
 {
-    if (colour == 0) met_sweep4_kernel<Q, 0, R><<<grid, 256, 0, s>>>(a);
-    else met_sweep4_kernel<Q, 1, R><<<grid, 256, 0, s>>>(a);
+    if (colour == 0) met_sweep4_kernel<Q, 0, R, LE><<<grid, 256, 0, s>>>(a, v, 0);
+    else met_sweep4_kernel<Q, 1, R, LE><<<grid, 256, 0, s>>>(a, v, fold);
 }
 
 template <int Q>
-void launch_quad(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
+void launch_quad(const LatticeArgs& a, const VolArgs& v, int colour, int fold, dim3 grid, hipStream_t s)
 {
-    if (a.quad == 2) launch_quad_r<Q, true>(a, colour, grid, s);
-    else launch_quad_r<Q, false>(a, colour, grid, s);
+    if (a.quad == 2) {
+        if (a.met_le) launch_quad_r<Q, true, true>(a, v, colour, fold, grid, s);
+        else launch_quad_r<Q, true, false>(a, v, colour, fold, grid, s);
+    } else {
+        if (a.met_le) launch_quad_r<Q, false, true>(a, v, colour, fold, grid, s);
+        else launch_quad_r<Q, false, false>(a, v, colour, fold, grid, s);
+    }
+}
+
+hipError_t launch_met_colour_fold(const LatticeArgs& a, const VolArgs& v, int colour, int fold, hipStream_t s)
+{
+    if (a.quad) {
+        const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
+        switch (a.q) {
+        case 2: launch_quad<2>(a, v, colour, fold, grid, s); break;
+        case 3: launch_quad<3>(a, v, colour, fold, grid, s); break;
+        case 4: launch_quad<4>(a, v, colour, fold, grid, s); break;
+        case 5: launch_quad<5>(a, v, colour, fold, grid, s); break;
+        default: launch_quad<6>(a, v, colour, fold, grid, s); break;
+        }
+        return hipGetLastError();
+    }
+    return launch_met_colour(a, colour, s);       // column pairs: no fold
 }
 
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
 {
     if (a.quad) {
-        const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
-        switch (a.q) {
-        case 2: launch_quad<2>(a, colour, grid, s); break;
-        case 3: launch_quad<3>(a, colour, grid, s); break;
-        case 4: launch_quad<4>(a, colour, grid, s); break;
-        case 5: launch_quad<5>(a, colour, grid, s); break;
-        default: launch_quad<6>(a, colour, grid, s); break;
-        }
-        return hipGetLastError();
+        VolArgs none{};
+        return launch_met_colour_fold(a, none, colour, 0, s);
     }
     const dim3 grid((a.L / 2 + 63) / 64, a.row_blocks), block(256);
     switch (a.q) {
@@ -532,10 +558,10 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s)
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, const VolArgs& v, int fold, hipStream_t s)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a);
+    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a, v, fold);
     return hipGetLastError();
 }
 

@@ -21,7 +21,10 @@
 // indexes an LDS table holding the acceptance threshold and a packed
 // counter increment (dc + 2^10 dh + 2^20 for one accepted move).
 // ---------------------------------------------------------------------------
-template <int Q>
+// LE: the table holds thr - 1 (2^32 - 1 for "always"), valid when no
+// threshold is 0, and a move is accepted iff word <= entry -- one compare
+// instead of clamping the word below the sentinel first.
+template <int Q, bool LE = false>
 __device__ __forceinline__ void met_arm(uint32_t& s4, uint32_t Z, uint32_t prop, uint32_t accw,
                                         const uint2* tbl, uint32_t& wsum)
 {
@@ -39,7 +42,7 @@ __device__ __forceinline__ void met_arm(uint32_t& s4, uint32_t Z, uint32_t prop,
     const uint32_t sn4 = min(t4, t4 - 4u * Q);            // mod q, in units of 4
     const int d = (int)__builtin_amdgcn_ubfe(Z, sn4, 4) - (int)__builtin_amdgcn_ubfe(Z, s4, 4);
     const uint2 e = tbl[d + 16];
-    bool acc = min(accw, 0xFFFFFFFEu) < e.x;              // thr == 2^32-1 always accepts
+    bool acc = LE ? accw <= e.x : min(accw, 0xFFFFFFFEu) < e.x;   // thr == 2^32-1 always accepts
     if (kHasNull) acc = acc && prop != 0xFFFFFFFFu;       // the NULL proposal
     s4 = acc ? sn4 : s4;
     wsum += acc ? e.y : 0u;
@@ -69,31 +72,42 @@ struct CellBytes {
     uint32_t s0, s1, s2, s3, f0, f1, f2, f3;
 };
 
-// Loads for the cell at column x of row y (wave-uniform y: every row/plane
-// offset is a scalar register).
+// Loads for the cell at column x of row y.  Row offsets go into the
+// wave-uniform scalar offset when y is the same for the whole wavefront, or
+// (VROW) into the per-lane offset when every lane has a row of its own.
+template <bool VROW>
+struct RowSplit {
+    // per-lane part and scalar part of the offset of column x in the row at o
+    __device__ __forceinline__ static uint32_t v(uint32_t x, uint32_t o) { return VROW ? x + o : x; }
+    __device__ __forceinline__ static uint32_t s(uint32_t base, uint32_t o) { return VROW ? base : base + o; }
+};
+
+template <bool VROW = false>
 __device__ __forceinline__ CellBytes met_load(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, uint32_t y,
                                               uint32_t x, uint32_t xp, uint32_t xm)
 {
+    using RS = RowSplit<VROW>;
     const uint32_t L = a.L, N = a.N;
     const uint32_t yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
-    const uint32_t o0 = y * L;
+    const uint32_t o0 = y * L, op = yp * L, om = ym * L;
     CellBytes b;
-    b.s0 = ld8(rs, x, o0);
-    b.s1 = ld8(rs, x, o0 + N);
-    b.s2 = ld8(rs, x, o0 + 2 * N);
-    b.s3 = ld8(rs, x, o0 + 3 * N);
-    b.f0 = ld8(rs, xp, o0 + N);                 // arm 1 of the +x neighbour
-    b.f1 = ld8(rs, xm, o0);                     // arm 0 of the -x neighbour
-    b.f2 = ld8(rs, x, 3 * N + yp * L);          // arm 3 of the +y neighbour
-    b.f3 = ld8(rs, x, 2 * N + ym * L);          // arm 2 of the -y neighbour
+    b.s0 = ld8(rs, RS::v(x, o0), RS::s(0, o0));
+    b.s1 = ld8(rs, RS::v(x, o0), RS::s(N, o0));
+    b.s2 = ld8(rs, RS::v(x, o0), RS::s(2 * N, o0));
+    b.s3 = ld8(rs, RS::v(x, o0), RS::s(3 * N, o0));
+    b.f0 = ld8(rs, RS::v(xp, o0), RS::s(N, o0));          // arm 1 of the +x neighbour
+    b.f1 = ld8(rs, RS::v(xm, o0), RS::s(0, o0));          // arm 0 of the -x neighbour
+    b.f2 = ld8(rs, RS::v(x, op), RS::s(3 * N, op));       // arm 3 of the +y neighbour
+    b.f3 = ld8(rs, RS::v(x, om), RS::s(2 * N, om));       // arm 2 of the -y neighbour
     return b;
 }
 
 // Update the four arms of the cell (x, y) from its loaded bytes and store them.
-template <int Q>
+template <int Q, bool VROW = false>
 __device__ __forceinline__ void met_cell(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, const uint2* tbl,
                                          uint32_t t, uint32_t y, uint32_t x, const CellBytes& b, uint32_t& wsum)
 {
+    using RS = RowSplit<VROW>;
     const uint32_t N = a.N, o0 = y * a.L;
     uint32_t s0 = b.s0 << 2, s1 = b.s1 << 2, s2 = b.s2 << 2, s3 = b.s3 << 2;
     const uint32_t f0 = b.f0 << 2, f1 = b.f1 << 2, f2 = b.f2 << 2, f3 = b.f3 << 2;
@@ -106,10 +120,10 @@ __device__ __forceinline__ void met_cell(const LatticeArgs& a, __amdgpu_buffer_r
     const uint32_t p01 = (1u << s0) + (1u << s1);
     met_arm<Q>(s2, p01 + (1u << s3) + (8u << f2), wb.x, wb.y, tbl, wsum);
     met_arm<Q>(s3, p01 + (1u << s2) + (8u << f3), wb.z, wb.w, tbl, wsum);
-    st8(rs, s0 >> 2, x, o0);
-    st8(rs, s1 >> 2, x, o0 + N);
-    st8(rs, s2 >> 2, x, o0 + 2 * N);
-    st8(rs, s3 >> 2, x, o0 + 3 * N);
+    st8(rs, s0 >> 2, RS::v(x, o0), RS::s(0, o0));
+    st8(rs, s1 >> 2, RS::v(x, o0), RS::s(N, o0));
+    st8(rs, s2 >> 2, RS::v(x, o0), RS::s(2 * N, o0));
+    st8(rs, s3 >> 2, RS::v(x, o0), RS::s(3 * N, o0));
 }
 
 // ---------------------------------------------------------------------------
@@ -181,22 +195,25 @@ struct QuadBytes {
 
 // ODD: y is odd.  With R the row of y is off a dword boundary when y is odd,
 // and its neighbour rows (y +- 1, wrapping to 0 or L-1) when y is even.
-template <int P, bool R, bool ODD>
+// VROW: row offsets per lane (see met_load; not combined with R).
+template <int P, bool R, bool ODD, bool VROW = false>
 __device__ __forceinline__ QuadBytes met_load4(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, uint32_t y,
                                                uint32_t x4, uint32_t x4h, uint32_t xl, uint32_t xr)
 {
+    static_assert(!(R && VROW), "ragged quads keep wave-uniform rows");
+    using RS = RowSplit<VROW>;
     constexpr bool DMIS = R && ODD, NMIS = R && !ODD;
     const uint32_t L = a.L, N = a.N;
     const uint32_t yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
-    const uint32_t o0 = y * L;
+    const uint32_t o0 = y * L, op = yp * L, om = ym * L;
     QuadBytes q;
-    q.d0 = ld32r<DMIS>(rs, x4, x4h, o0);
-    q.d1 = ld32r<DMIS>(rs, x4, x4h, o0 + N);
-    q.d2 = ld32r<DMIS>(rs, x4, x4h, o0 + 2 * N);
-    q.d3 = ld32r<DMIS>(rs, x4, x4h, o0 + 3 * N);
-    q.up3 = ld32r<NMIS>(rs, x4, x4h, 3 * N + yp * L);
-    q.dn2 = ld32r<NMIS>(rs, x4, x4h, 2 * N + ym * L);
-    q.edge = (P == 0) ? ld8(rs, xl, o0) : ld8(rs, xr, o0 + N);
+    q.d0 = ld32r<DMIS>(rs, RS::v(x4, o0), RS::v(x4h, o0), RS::s(0, o0));
+    q.d1 = ld32r<DMIS>(rs, RS::v(x4, o0), RS::v(x4h, o0), RS::s(N, o0));
+    q.d2 = ld32r<DMIS>(rs, RS::v(x4, o0), RS::v(x4h, o0), RS::s(2 * N, o0));
+    q.d3 = ld32r<DMIS>(rs, RS::v(x4, o0), RS::v(x4h, o0), RS::s(3 * N, o0));
+    q.up3 = ld32r<NMIS>(rs, RS::v(x4, op), RS::v(x4h, op), RS::s(3 * N, op));
+    q.dn2 = ld32r<NMIS>(rs, RS::v(x4, om), RS::v(x4h, om), RS::s(2 * N, om));
+    q.edge = (P == 0) ? ld8(rs, RS::v(xl, o0), RS::s(0, o0)) : ld8(rs, RS::v(xr, o0), RS::s(N, o0));
     return q;
 }
 
@@ -216,7 +233,7 @@ __device__ __forceinline__ uint32_t put2(uint32_t d, uint32_t v1, uint32_t v2)
     return (d & keep) | w1 | (v2 << (8 * B2 - 2));
 }
 
-template <int Q, int P, bool R, bool ODD>
+template <int Q, int P, bool R, bool ODD, bool LE = false, bool VROW = false>
 __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, const uint2* tbl,
                                          uint32_t t, uint32_t y, uint32_t x4, const QuadBytes& q, uint32_t& wsum,
                                          bool ragged)
@@ -237,11 +254,11 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
         const uint4 wa = philox(c, t, 0u, kStreamMet, a.key0, a.key1);
         const uint4 wb = philox(c, t, 1u, kStreamMet, a.key0, a.key1);
         const uint32_t p23 = (1u << a2) + (1u << a3);
-        met_arm<Q>(a0, p23 + (1u << a1) + (8u << f0), wa.x, wa.y, tbl, wsum);
-        met_arm<Q>(a1, p23 + (1u << a0) + (8u << f1), wa.z, wa.w, tbl, wsum);
+        met_arm<Q, LE>(a0, p23 + (1u << a1) + (8u << f0), wa.x, wa.y, tbl, wsum);
+        met_arm<Q, LE>(a1, p23 + (1u << a0) + (8u << f1), wa.z, wa.w, tbl, wsum);
         const uint32_t p01 = (1u << a0) + (1u << a1);
-        met_arm<Q>(a2, p01 + (1u << a3) + (8u << f2), wb.x, wb.y, tbl, wsum);
-        met_arm<Q>(a3, p01 + (1u << a2) + (8u << f3), wb.z, wb.w, tbl, wsum);
+        met_arm<Q, LE>(a2, p01 + (1u << a3) + (8u << f2), wb.x, wb.y, tbl, wsum);
+        met_arm<Q, LE>(a3, p01 + (1u << a2) + (8u << f3), wb.z, wb.w, tbl, wsum);
     }
     const uint32_t wkeep = wsum;                      // R: the last quad's second cell is a phantom
     {
@@ -252,18 +269,20 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
         const uint4 wa = philox(c, t, 0u, kStreamMet, a.key0, a.key1);
         const uint4 wb = philox(c, t, 1u, kStreamMet, a.key0, a.key1);
         const uint32_t p23 = (1u << b2) + (1u << b3);
-        met_arm<Q>(b0, p23 + (1u << b1) + (8u << f0), wa.x, wa.y, tbl, wsum);
-        met_arm<Q>(b1, p23 + (1u << b0) + (8u << f1), wa.z, wa.w, tbl, wsum);
+        met_arm<Q, LE>(b0, p23 + (1u << b1) + (8u << f0), wa.x, wa.y, tbl, wsum);
+        met_arm<Q, LE>(b1, p23 + (1u << b0) + (8u << f1), wa.z, wa.w, tbl, wsum);
         const uint32_t p01 = (1u << b0) + (1u << b1);
-        met_arm<Q>(b2, p01 + (1u << b3) + (8u << f2), wb.x, wb.y, tbl, wsum);
-        met_arm<Q>(b3, p01 + (1u << b2) + (8u << f3), wb.z, wb.w, tbl, wsum);
+        met_arm<Q, LE>(b2, p01 + (1u << b3) + (8u << f2), wb.x, wb.y, tbl, wsum);
+        met_arm<Q, LE>(b3, p01 + (1u << b2) + (8u << f3), wb.z, wb.w, tbl, wsum);
     }
     if (R && ragged) wsum = wkeep;
     constexpr bool DMIS = R && ODD;
-    st32r<R, DMIS>(rs, put2<B1, B2>(q.d0, a0, b0), x4, o0, ragged);
-    st32r<R, DMIS>(rs, put2<B1, B2>(q.d1, a1, b1), x4, o0 + N, ragged);
-    st32r<R, DMIS>(rs, put2<B1, B2>(q.d2, a2, b2), x4, o0 + 2 * N, ragged);
-    st32r<R, DMIS>(rs, put2<B1, B2>(q.d3, a3, b3), x4, o0 + 3 * N, ragged);
+    using RS = RowSplit<VROW>;
+    const uint32_t xv = RS::v(x4, o0);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d0, a0, b0), xv, RS::s(0, o0), ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d1, a1, b1), xv, RS::s(N, o0), ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d2, a2, b2), xv, RS::s(2 * N, o0), ragged);
+    st32r<R, DMIS>(rs, put2<B1, B2>(q.d3, a3, b3), xv, RS::s(3 * N, o0), ragged);
 }
 
 __device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int theta)
@@ -281,6 +300,23 @@ __device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int 
         tbl[tid] = e;
     }
     __syncthreads();
+}
+
+// Entry i (0..63) of the two-theta table: theta = i / 32, index d + 16 with
+// d = dc + 8 dh; entries that no (dc, dh) reaches hold 0.
+template <bool LE>
+__device__ __forceinline__ uint2 met_table_entry(const LatticeArgs& a, int i)
+{
+    const int th = i >> 5, dd = (i & 31) - 16;
+    const int dh = (dd + 4) >> 3;
+    const int dc = dd - 8 * dh;
+    uint2 e = make_uint2(0u, 0u);
+    if (dd >= -11 && dd <= 11 && dc >= -3 && dc <= 3) {
+        const uint32_t thr = a.tab->met[th][(dh + 1) * 7 + dc + 3];
+        e.x = LE ? (thr == 0xFFFFFFFFu ? thr : thr - 1u) : thr;
+        e.y = (uint32_t)(dc + (dh << 10) + (1 << 20));
+    }
+    return e;
 }
 
 __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32_t slot)
@@ -319,23 +355,37 @@ struct ProgressPrio {
     }
 };
 
-// One workgroup's share of a colour pass with quad lanes: column group bx
-// (64 quads), row segments 4 by .. 4 by + 3 (one per wavefront).  The first
-// row's loads are issued before the LDS table is built, so both latencies
-// overlap.  Returns the lane's packed counter sum.
-template <int Q, int KAPPA, bool PRIO, bool R>
-__device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* tbl, uint32_t t, int theta,
-                                                   uint32_t bx, uint32_t by)
+// No occupancy cap: the quad loop needs ~84 VGPRs (5 wavefronts per SIMD).
+// Caps measured slower (64 VGPRs for 7 wavefronts without spills, or 8 with
+// a small spill).  At L = 4096 the host picks 16 rows per wavefront: 1024
+// workgroups, all resident at once.
+//
+// Start-up: nothing the first row's loads and the table need depends on the
+// chain state, so the table entries of both theta values and the first row
+// are requested before the state (skip flag, theta, step) is read, and the
+// first wait covers all three at once.
+//
+// fold (colour 1 only): the workgroup that finishes last -- a counter in the
+// chain state, incremented by every workgroup after its counter atomics have
+// completed -- folds the slots and performs the next step's volume move,
+// which otherwise is a launch of its own between two sweeps.
+template <int Q, int KAPPA, bool R, bool LE>
+__global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a, VolArgs va, int fold)
 {
+    __shared__ uint2 tbl[64];
+    __shared__ double term[40];
+    const uint32_t tid = threadIdx.x;
+    uint2 e = make_uint2(0u, 0u);
+    if (tid < 64) e = met_table_entry<LE>(a, (int)tid);
     const uint32_t L = a.L;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t j = bx * 64 + lane;
-    const uint32_t y0 = (by * 4 + wave) * a.rows;      // even
-    const bool active = j < ((L + 3) >> 2) && y0 < L;   // (L + 2) / 4 quads when R
+    const uint32_t lane = tid & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t j = blockIdx.x * 64 + lane;
+    const uint32_t y0 = (blockIdx.y * 4 + wave) * a.rows;      // even
+    const bool active = j < ((L + 3) >> 2) && y0 < L;           // (L + 2) / 4 quads when R
     const uint32_t x4 = 4 * j;
     const bool ragged = R && x4 + 2 == L;
-    const uint32_t x4h = ragged ? x4 : x4 + 2;         // high halves of off-boundary rows
+    const uint32_t x4h = ragged ? x4 : x4 + 2;                 // high halves of off-boundary rows
     const uint32_t xl = (x4 == 0) ? L - 1 : x4 - 1, xr = (x4 + 4 >= L) ? 0 : x4 + 4;
     const uint32_t y1 = min(y0 + a.rows, L);
     const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
@@ -343,35 +393,36 @@ __device__ __forceinline__ uint32_t met_quad_block(const LatticeArgs& a, uint2* 
     constexpr int PE = KAPPA, PO = 1 - KAPPA;
     QuadBytes cur = {};
     if (active) cur = met_load4<PE, R, false>(a, rs, y0, x4, x4h, xl, xr);
-    met_table(a, tbl, theta);
+    const int skip = a.st->skip, theta = a.st->theta;
+    const uint32_t t = a.st->t_cur;
+    if (tid < 64) tbl[tid] = e;
+    __syncthreads();
+    if (skip) return;                                          // step limit reached (uniform)
+    const uint2* tb = tbl + (theta ? 32 : 0);
     uint32_t wsum = 0;
     if (active) {
-        const ProgressPrio<PRIO> prio((y1 - y0) >> 1);
+        const ProgressPrio<true> prio((y1 - y0) >> 1);
         for (uint32_t y = y0; y < y1; y += 2) {
             prio.step((y - y0) >> 1);
             const QuadBytes odd = met_load4<PO, R, true>(a, rs, y + 1, x4, x4h, xl, xr);
-            met_quad<Q, PE, R, false>(a, rs, tbl, t, y, x4, cur, wsum, ragged);
+            met_quad<Q, PE, R, false, LE>(a, rs, tb, t, y, x4, cur, wsum, ragged);
             const uint32_t yn = (y + 2 < y1) ? y + 2 : y;
             cur = met_load4<PE, R, false>(a, rs, yn, x4, x4h, xl, xr);
-            met_quad<Q, PO, R, true>(a, rs, tbl, t, y + 1, x4, odd, wsum, ragged);
+            met_quad<Q, PO, R, true, LE>(a, rs, tb, t, y + 1, x4, odd, wsum, ragged);
         }
     }
-    return wsum;
-}
-
-// No occupancy cap: the quad loop needs ~84 VGPRs (5 wavefronts per SIMD).
-// Caps measured slower (64 VGPRs for 7 wavefronts without spills, or 8 with
-// a small spill).  At L = 4096 the host picks 16 rows per wavefront: 1024
-// workgroups, all resident at once.
-template <int Q, int KAPPA, bool R>
-__global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
-{
-    const int skip = a.st->skip, theta = a.st->theta;
-    const uint32_t t = a.st->t_cur;
-    if (skip) return;                                      // step limit reached
-    __shared__ uint2 tbl[32];
-    const uint32_t wsum = met_quad_block<Q, KAPPA, true, R>(a, tbl, t, theta, blockIdx.x, blockIdx.y);
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
+    // The workgroup's counter atomics were issued by wave 0; once they are
+    // performed (release fence) lane 0 counts the workgroup as finished.
+    if (!fold || tid >= 64) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t total = gridDim.x * gridDim.y;
+    uint32_t prev = 0;
+    if (tid == 0) prev = atomicInc(&a.st->arrive, total - 1);     // wraps to 0 for the next launch
+    prev = (uint32_t)__shfl((int)prev, 0, 64);
+    if (prev != total - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    volume_step<true>(va, term);
 }
 
 // Byte-lane variant (any even L): lane i owns the column pair (2i, 2i+1).
@@ -427,13 +478,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 // ---------------------------------------------------------------------------
-// Batched colour pass: many independent chains in one launch.  Workgroup b
-// belongs to the chain c with start[c] <= b < start[c+1]; inside the chain it
-// is the workgroup (bx, by) of that chain's own launch shape, so every chain
-// computes exactly what its own launch computes.
+// Batched colour pass: many independent chains of uneven L in one launch.
+// Workgroup b belongs to the chain c with start[c] <= b < start[c+1].
+// A chain's colour pass is cut into work units -- a row pair (2 rp, 2 rp + 1)
+// times a column quad (L % 4 == 0) or a column pair (L % 4 == 2) -- numbered
+// row pair major, and lane l of wavefront w of the chain's workgroup k moves
+// the units (4 k + w) 64 K + l + 64 i, i < K.  No lane idles on a short row:
+// a wavefront spans as many rows as 64 units cover (four row pairs of an
+// L = 64 lattice), and only the chain's last wavefront can run out of units.
+// Every unit is moved exactly as the chain's own launch moves it (same
+// Philox counters, same update order inside a cell; cells of one colour do
+// not interact), so each chain follows its standalone trajectory bit for bit.
 // ---------------------------------------------------------------------------
-// Batches are mostly small lattices (many workgroups of few rows): here the
-// 8-wavefront occupancy measured faster than the uncapped register budget.
+// Batches are mostly small lattices: the 8-wavefront occupancy measured
+// faster than the uncapped register budget.
 template <int Q, int KAPPA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_batch_kernel(
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ start, uint32_t count)
@@ -449,12 +507,85 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const int skip = a.st->skip, theta = a.st->theta;
     const uint32_t t = a.st->t_cur;
     if (skip) return;                                      // step limit reached
+    const uint32_t units = ent[lo].units, upr = ent[lo].upr, K = ent[lo].iters;
+    const double upr_inv = ent[lo].upr_inv;
     const uint32_t local = blockIdx.x - start[lo];
-    const uint32_t gx = ent[lo].groups_x;
-    const uint32_t by = local / gx, bx = local - by * gx;
-    // (batches move L % 4 == 2 lattices in column pairs: quad is 0 or 1 here)
-    const uint32_t wsum = a.quad ? met_quad_block<Q, KAPPA, false, false>(a, tbl, t, theta, bx, by)
-                                 : met_byte_block<Q, false>(a, tbl, t, theta, KAPPA, bx, by);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t first = (local * 4 + wave) * 64 * K + lane;
+    const uint32_t L = a.L;
+    const __amdgpu_buffer_rsrc_t rs = sigma_rsrc(a.sigma, 4 * a.N);
+    uint32_t wsum = 0;
+    if (a.quad) {
+        constexpr int PE = KAPPA, PO = 1 - KAPPA;
+        auto at = [&](uint32_t u, uint32_t& y, uint32_t& x4, uint32_t& xl, uint32_t& xr) {
+            uint32_t qd;
+            y = 2 * divmod(u, upr, upr_inv, qd);
+            x4 = 4 * qd;
+            xl = (x4 == 0) ? L - 1 : x4 - 1;
+            xr = (x4 + 4 >= L) ? 0 : x4 + 4;
+        };
+        uint32_t y, x4, xl, xr;
+        at(first, y, x4, xl, xr);
+        QuadBytes cur = {};
+        if (first < units) cur = met_load4<PE, false, false, true>(a, rs, y, x4, x4 + 2, xl, xr);
+        met_table(a, tbl, theta);
+        for (uint32_t i = 0; i < K; ++i) {
+            const uint32_t u = first + 64 * i;
+            const bool act = u < units;
+            QuadBytes odd = {};
+            if (act) {
+                odd = met_load4<PO, false, true, true>(a, rs, y + 1, x4, x4 + 2, xl, xr);
+                met_quad<Q, PE, false, false, false, true>(a, rs, tbl, t, y, x4, cur, wsum, false);
+            }
+            const uint32_t un = u + 64;
+            uint32_t yn, x4n, xln, xrn;
+            at(un, yn, x4n, xln, xrn);
+            if (i + 1 < K && un < units) cur = met_load4<PE, false, false, true>(a, rs, yn, x4n, x4n + 2, xln, xrn);
+            if (act) met_quad<Q, PO, false, true, false, true>(a, rs, tbl, t, y + 1, x4, odd, wsum, false);
+            y = yn;
+            x4 = x4n;
+            xl = xln;
+            xr = xrn;
+        }
+    } else {
+        // column pairs: the updated cell of a pair sits at column 2 pr + KAPPA
+        // in even rows and 2 pr + 1 - KAPPA in odd rows
+        auto at = [&](uint32_t u, uint32_t& y, uint32_t& pr) { y = 2 * divmod(u, upr, upr_inv, pr); };
+        auto nb = [&](uint32_t x, uint32_t& xp, uint32_t& xm) {
+            xp = (x + 1 == L) ? 0 : x + 1;
+            xm = (x == 0) ? L - 1 : x - 1;
+        };
+        uint32_t y, pr, xp, xm;
+        at(first, y, pr);
+        CellBytes cur = {};
+        if (first < units) {
+            nb(2 * pr + KAPPA, xp, xm);
+            cur = met_load<true>(a, rs, y, 2 * pr + KAPPA, xp, xm);
+        }
+        met_table(a, tbl, theta);
+        for (uint32_t i = 0; i < K; ++i) {
+            const uint32_t u = first + 64 * i;
+            const bool act = u < units;
+            const uint32_t xA = 2 * pr + KAPPA, xB = 2 * pr + (1 - KAPPA);
+            CellBytes odd = {};
+            if (act) {
+                nb(xB, xp, xm);
+                odd = met_load<true>(a, rs, y + 1, xB, xp, xm);
+                met_cell<Q, true>(a, rs, tbl, t, y, xA, cur, wsum);
+            }
+            const uint32_t un = u + 64;
+            uint32_t yn, prn;
+            at(un, yn, prn);
+            if (i + 1 < K && un < units) {
+                nb(2 * prn + KAPPA, xp, xm);
+                cur = met_load<true>(a, rs, yn, 2 * prn + KAPPA, xp, xm);
+            }
+            if (act) met_cell<Q, true>(a, rs, tbl, t, y + 1, xB, odd, wsum);
+            y = yn;
+            pr = prn;
+        }
+    }
     met_reduce(wsum, a.slots, local);
 }
 

@@ -680,11 +680,26 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     block_add<2, kTT>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
 }
 
-__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
+// fold: the workgroup that finishes last (a counter in the chain state,
+// incremented once the workgroup's counter atomics are performed) folds the
+// slots -- the recount of the new configuration -- and opens the next step
+// with its volume move, which otherwise is a launch of its own.
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(
+    LatticeArgs a, VolArgs va, int fold)
 {
     if (a.st->skip) return;
     __shared__ FlipLds lds;
+    __shared__ double term[40];
     sw_flip_body(a, grid_tile(a.L), lds);
+    if (!fold || threadIdx.x >= 64) return;                // block_add's atomics are wave 0's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t total = gridDim.x * gridDim.y;
+    uint32_t prev = 0;
+    if (threadIdx.x == 0) prev = atomicInc(&a.st->arrive, total - 1);
+    prev = (uint32_t)__shfl((int)prev, 0, 64);
+    if (prev != total - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    volume_step<true>(va, term);
 }
 
 // label[idx] = the minimum of idx's cluster, for every bond index; written
