@@ -114,9 +114,10 @@ int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
  * acceptance table.  Swendsen-Wang (Sec. II.D) adds the state of its
  * labelling -- the paper's bond array and label array of every bond index
  * -- as 25 bytes per cell (uint32 labels and uint16 tile-local roots of the
- * 4N bond indices, one bond mask byte per cell) and 96 bytes per 64 x
- * 32-cell tile.  Host only.  CVF_EINVAL for a NULL argument, invalid
- * parameters or an empty algo_mask. */
+ * 4N bond indices, one bond mask byte per cell) and 872 bytes per 64 x
+ * 32-cell tile (edge bytes, the words two tiles exchange for the links
+ * between them, arrival counters).  Host only.  CVF_EINVAL for a NULL
+ * argument, invalid parameters or an empty algo_mask. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
 
 /* Create a chain.  d_sigma: 4*L*L bytes of device memory (4-byte aligned:
@@ -224,8 +225,11 @@ int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
  * launches and their mean duration in ms since timing was enabled. */
 #define CVF_K_VOLUME    0   /* volume move / counter fold          */
 #define CVF_K_MET_SWEEP 1   /* one checkerboard colour sweep       */
-#define CVF_K_SW_BONDS  2   /* bond activation + in-tile labels    */
-#define CVF_K_SW_UNION  3   /* tile-crossing covalent unions       */
+#define CVF_K_SW_BONDS  2   /* bond activation + in-tile labels
+                               + the tile-crossing unions          */
+#define CVF_K_SW_UNION  3   /* not launched: the tile-crossing
+                               unions run in the CVF_K_SW_BONDS
+                               launch (value kept for the ABI)     */
 #define CVF_K_SW_FLIP   4   /* cluster shift + recount             */
 #define CVF_K_RECOUNT   5   /* lattice recount (separate launches) */
 #define CVF_K_MET_DOMAIN 6  /* one arm-domain pass                 */

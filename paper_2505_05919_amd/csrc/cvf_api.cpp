@@ -28,6 +28,8 @@ struct cvf_state {
     uint8_t* mask;
     uint8_t* edge;
     uint16_t* lroot;
+    uint32_t* xchg;
+    uint32_t* ecnt;
     DevTables htab;          // host copy (source of the init copy, test hook)
     LatticeArgs la;
     VolArgs va;
@@ -210,6 +212,8 @@ void chain_setup(const cvf_params* p, uint8_t* d_sigma, char* work, size_t work_
     st->mask = st->has_sw ? (uint8_t*)(st->work + kBaseBytes + align256(4ull * st->N * sizeof(uint32_t))) : nullptr;
     st->edge = st->has_sw ? st->mask + align256(st->N) : nullptr;
     st->lroot = st->has_sw ? (uint16_t*)(st->edge + align256(sw_tiles((uint64_t)p->L) * kEdgeBytes)) : nullptr;
+    st->xchg = st->has_sw ? (uint32_t*)((char*)st->lroot + align256(4ull * st->N * sizeof(uint16_t))) : nullptr;
+    st->ecnt = st->has_sw ? st->xchg + align256(sw_tiles((uint64_t)p->L) * kBorderIdx * sizeof(uint32_t)) / 4 : nullptr;
     build_tables(p, &st->htab);
 
     const double Jeff = p->J - p->P * p->vHB;
@@ -224,6 +228,8 @@ void chain_setup(const cvf_params* p, uint8_t* d_sigma, char* work, size_t work_
     a.mask = st->mask;
     a.edge = st->edge;
     a.lroot = st->lroot;
+    a.xchg = st->xchg;
+    a.ecnt = st->ecnt;
     a.L = (uint32_t)p->L;
     a.N = st->N;
     a.key0 = (uint32_t)p->seed;
@@ -271,6 +277,7 @@ hipError_t chain_start(cvf_state* st, bool tables_by_kernel, hipStream_t s)
                                     : hipMemcpyAsync(st->dtab, &st->htab, sizeof(DevTables), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_state_init(st->dst, st->slots, st->dtab, st->p.v_init, s);
     if (e == hipSuccess && !(st->p.flags & CVF_KEEP_SIGMA)) e = launch_sigma_init(st->la, s);
+    if (e == hipSuccess && st->has_sw) e = launch_sw_counters_init(st->la, s);
     if (e == hipSuccess) e = launch_recount(st->la, st->slots, kSlots, 0, 0, s);
     return e;
 }
@@ -305,14 +312,10 @@ int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
     VolArgs v = st->va;
     v.mode = kVolMet;
     v.met_att_add = 4 * (int64_t)st->N;
-    // Quad lanes: the colour-1 launch of every sweep but the last opens the
-    // next step in its last workgroup, so the volume move is a launch of its
-    // own only once per call.
-    const bool fold = st->la.quad != 0;
     for (int64_t i = 0; i < nsweeps; ++i) {
-        if (i == 0 || !fold) TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour_fold(st->la, v, 0, 0, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour_fold(st->la, v, 1, fold && i + 1 < nsweeps, s));
+        TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 0, s));
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 1, s));
     }
     return CVF_OK;
 }
@@ -339,13 +342,10 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     VolArgs v = st->va;
     v.mode = kVolSw;
-    // the flip launch of every step but the last opens the next step in its
-    // last workgroup: the volume move is a launch of its own once per call
     for (int64_t i = 0; i < nsteps; ++i) {
-        if (i == 0) TIMED(CVF_K_VOLUME, launch_volume(v, s));
+        TIMED(CVF_K_VOLUME, launch_volume(v, s));
         TIMED(CVF_K_SW_BONDS, launch_sw_tiles(st->la, s));
-        TIMED(CVF_K_SW_UNION, launch_sw_union_edges(st->la, s));
-        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, v, i + 1 < nsteps, s));
+        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, s));
     }
     return CVF_OK;
 }
@@ -463,16 +463,14 @@ struct cvf_batch {
     std::vector<BatchEntry> host;     // descriptor source (kept alive for async copies)
     std::vector<uint32_t> start;      // prefix sums of Metropolis workgroups, count + 1
     std::vector<uint32_t> tstart;     // prefix sums of SW tiles, count + 1
-    std::vector<uint32_t> estart;     // prefix sums of SW edge-union workgroups, count + 1
     BatchEntry* d_ent;
     uint32_t* d_start;
     uint32_t* d_tstart;
-    uint32_t* d_estart;
     uint32_t total_blocks;
     uint32_t sw_tiles;
-    uint32_t sw_edge_blocks;
     bool has_sw;
     int q;
+    int le;                           // every chain's table allows the one-compare acceptance
     int32_t rows;                     // 0 = per-chain default
     hipStream_t capture;              // private stream for graph capture
     hipGraphExec_t exec;
@@ -481,16 +479,15 @@ struct cvf_batch {
 
 namespace {
 
-// Descriptor: the entries, then three prefix-sum arrays (Metropolis
-// workgroups, SW tiles, SW edge workgroups).
-size_t batch_layout(int32_t count, size_t* off_start, size_t* off_tstart, size_t* off_estart)
+// Descriptor: the entries, then two prefix-sum arrays (Metropolis
+// workgroups, SW tiles).
+size_t batch_layout(int32_t count, size_t* off_start, size_t* off_tstart)
 {
     const size_t ent = align256((size_t)count * sizeof(BatchEntry));
     const size_t st = align256(((size_t)count + 1) * sizeof(uint32_t));
     *off_start = ent;
     *off_tstart = ent + st;
-    *off_estart = ent + 2 * st;
-    return ent + 3 * st;
+    return ent + 2 * st;
 }
 
 
@@ -507,8 +504,7 @@ int batch_upload(cvf_batch* b, hipStream_t s)
     b->host.resize(count);
     b->start.assign(count + 1, 0);
     b->tstart.assign(count + 1, 0);
-    b->estart.assign(count + 1, 0);
-    uint32_t total = 0, ttotal = 0, etotal = 0;
+    uint32_t total = 0, ttotal = 0;
     for (uint32_t c = 0; c < count; ++c) {
         const cvf_state* st = b->chains[c];
         BatchEntry& e = b->host[c];
@@ -535,22 +531,16 @@ int batch_upload(cvf_batch* b, hipStream_t s)
         const uint32_t ncx = (L + kTW - 1) / kTW, ncy = (L + kTH - 1) / kTH;
         b->tstart[c] = ttotal;
         ttotal += ncx * ncy;
-        b->estart[c] = etotal;
-        etotal += (uint32_t)(((uint64_t)(ncx + ncy) * L + 255) / 256);
     }
     b->start[count] = total;
     b->tstart[count] = ttotal;
-    b->estart[count] = etotal;
     b->total_blocks = total;
     b->sw_tiles = ttotal;
-    b->sw_edge_blocks = etotal;
     hipError_t e = hipMemcpyAsync(b->d_ent, b->host.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_start, b->start.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_tstart, b->tstart.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_estart, b->estart.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     // the host vectors must stay unchanged until the copies are done
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_status(e);
@@ -560,8 +550,8 @@ hipError_t batch_sweep(cvf_batch* b, hipStream_t s)
 {
     const uint32_t count = (uint32_t)b->chains.size();
     hipError_t e = launch_volume_batch(b->d_ent, count, kVolMet, s);
-    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 0, s);
-    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 1, s);
+    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 0, b->le, s);
+    if (e == hipSuccess) e = launch_met_batch(b->d_ent, b->d_start, count, b->total_blocks, b->q, 1, b->le, s);
     return e;
 }
 
@@ -588,8 +578,8 @@ int batch_capture(cvf_batch* b, int32_t block)
 int cvf_batch_desc_bytes(int32_t count, size_t* bytes)
 {
     if (!bytes || count <= 0) return CVF_EINVAL;
-    size_t off, off2, off3;
-    *bytes = batch_layout(count, &off, &off2, &off3);
+    size_t off, off2;
+    *bytes = batch_layout(count, &off, &off2);
     return CVF_OK;
 }
 
@@ -598,8 +588,8 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
 {
     if (!chains || count <= 0 || !d_desc || !out) return CVF_EINVAL;
     if (((uintptr_t)d_desc & 255) != 0) return CVF_EINVAL;
-    size_t off_start, off_tstart, off_estart;
-    if (desc_bytes < batch_layout(count, &off_start, &off_tstart, &off_estart)) return CVF_ENOMEM;
+    size_t off_start, off_tstart;
+    if (desc_bytes < batch_layout(count, &off_start, &off_tstart)) return CVF_ENOMEM;
     for (int32_t c = 0; c < count; ++c)
         if (!chains[c] || chains[c]->p.q != chains[0]->p.q || (chains[c]->p.L & 1)) return CVF_EINVAL;
     cvf_batch* b = new (std::nothrow) cvf_batch();
@@ -608,8 +598,10 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
     b->d_ent = (BatchEntry*)d_desc;
     b->d_start = (uint32_t*)((char*)d_desc + off_start);
     b->d_tstart = (uint32_t*)((char*)d_desc + off_tstart);
-    b->d_estart = (uint32_t*)((char*)d_desc + off_estart);
     b->q = chains[0]->p.q;
+    b->le = 1;
+    for (int32_t c = 0; c < count; ++c)
+        if (!chains[c]->la.met_le) b->le = 0;
     b->has_sw = true;
     for (int32_t c = 0; c < count; ++c) b->has_sw = b->has_sw && chains[c]->has_sw && chains[c]->p.Jsigma >= 0.0;
     b->rows = 0;
@@ -664,7 +656,6 @@ int cvf_batch_sw_steps(cvf_batch* b, int64_t nsteps, void* stream)
     for (int64_t i = 0; i < nsteps; ++i) {
         hipError_t e = launch_volume_batch(b->d_ent, count, kVolSw, s);
         if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_tstart, count, b->sw_tiles, 0, s);
-        if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_estart, count, b->sw_edge_blocks, 1, s);
         if (e == hipSuccess) e = launch_sw_batch(b->d_ent, b->d_tstart, count, b->sw_tiles, 2, s);
         if (e != hipSuccess) return CVF_EHIP;
     }

@@ -45,8 +45,6 @@ struct DevState {
     int32_t sw_done;         // a Swendsen-Wang step has produced labels
     int32_t skip;            // 1: the step limit is reached, step kernels do nothing
     int64_t stop_at;         // no step with index >= stop_at is performed
-    uint32_t arrive;         // workgroups of the current colour-1 launch that have finished (wraps to 0)
-    uint32_t pad_;
 };
 
 // Host-computed constants copied to the workspace at init.
@@ -70,15 +68,25 @@ constexpr size_t kOffTables = kOffSlots + 3 * kSlots * sizeof(int64_t);   // 640
 constexpr size_t kOffObs = kOffTables + 768;                                // 7168
 constexpr size_t kBaseBytes = kOffObs + 512;                                // 7680
 
-// Swendsen-Wang part of a workspace: labels (4N uint32), bond mask (N bytes),
-// per-tile edge bytes, tile-local roots (4N uint16), each 256-aligned.
+// Border bond indices of a tile (the ends of its tile-crossing links):
+// arm 0 of the last column and arm 1 of the first (one per row), arm 2 of
+// the last row and arm 3 of the first (one per column).
+constexpr uint32_t kBorderIdx = 2 * (kTW + kTH);
+
+// Swendsen-Wang part of a workspace, each piece 256-aligned: labels (4N
+// uint32), bond mask (N bytes), per-tile edge bytes, tile-local roots (4N
+// uint16), per-tile exchange words (kBorderIdx uint32: the global root of
+// each border bond index, or kNoLink), per-tile edge counters (2 uint32).
 constexpr size_t align256c(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t sw_tiles_of(uint64_t L) { return ((L + kTW - 1) / kTW) * ((L + kTH - 1) / kTH); }
 constexpr size_t sw_bytes_of(uint64_t L)
 {
     return align256c(4 * L * L * sizeof(uint32_t)) + align256c(L * L) + align256c(sw_tiles_of(L) * kEdgeBytes) +
-           align256c(4 * L * L * sizeof(uint16_t));
+           align256c(4 * L * L * sizeof(uint16_t)) + align256c(sw_tiles_of(L) * kBorderIdx * sizeof(uint32_t)) +
+           align256c(sw_tiles_of(L) * 2 * sizeof(uint32_t));
 }
+// An exchange word that names no link (flat indices are at most 4N - 1 <= 2^32 - 2).
+constexpr uint32_t kNoLink = 0xFFFFFFFFu;
 
 // The allocation-free entry point keeps a whole Swendsen-Wang workspace for
 // lattices up to kNoAllocMaxL in one fixed device array.
@@ -99,6 +107,8 @@ struct LatticeArgs {
     uint8_t* mask;           // Swendsen-Wang only
     uint8_t* edge;           // Swendsen-Wang only: kEdgeBytes per tile
     uint16_t* lroot;         // Swendsen-Wang only: tile-local root of every bond index (| border flag)
+    uint32_t* xchg;          // Swendsen-Wang only: kBorderIdx exchange words per tile
+    uint32_t* ecnt;          // Swendsen-Wang only: arrival counters of each tile's right and bottom edge
     uint32_t L, N;           // side, L*L
     uint32_t key0, key1;     // Philox key (seed)
     uint32_t q;
@@ -150,9 +160,6 @@ hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_volume(const VolArgs& a, hipStream_t s);
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
-// The checkerboard sweep with quad lanes: colour 1 with fold != 0 also opens
-// the next step (counter fold + volume move, `v`) in its last workgroup.
-hipError_t launch_met_colour_fold(const LatticeArgs& a, const VolArgs& v, int colour, int fold, hipStream_t s);
 // Arm-domain sweep: pass 0..3 of the step's drawn arm order (any L >= 2).
 hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s);
 // step_gate: the recount closes an SW step and is skipped with it.
@@ -163,22 +170,23 @@ hipError_t launch_obs_zero(DevObs* o, hipStream_t s);
 hipError_t launch_state_counts(const LatticeArgs& a, int64_t* out, hipStream_t s);
 hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab, double Nd, double J,
                             double Jsigma, double P, double vHB, hipStream_t s);
-// Tiled SW step: bonds + in-tile unions, the tile-crossing links, then the
-// cluster shift fused with the recount.  Labels are written out on request.
+// Tiled SW step: bonds + in-tile unions + the tile-crossing links (each
+// united by the later of its two tiles), then the cluster shift fused with
+// the recount.  Labels are written out on request.
 hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s);
-// fold != 0: the last workgroup also opens the next step (volume move `v`).
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, const VolArgs& v, int fold, hipStream_t s);
+// Zero the edge arrival counters (once, when the chain is created).
+hipError_t launch_sw_counters_init(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s);
 hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,
-// count+1 prefix sums of workgroups); all chains share q.
+// count+1 prefix sums of workgroups); all chains share q; le: every chain's
+// table allows the one-compare acceptance.
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
-                            int q, int colour, hipStream_t s);
+                            int q, int colour, int le, hipStream_t s);
 hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s);
-// Batched Swendsen-Wang stage: 0 tiles (bonds + in-tile unions), 1 tile-
-// crossing links, 2 shift + recount; start: count+1 prefix sums of the
-// per-chain workgroups of that stage (tiles for 0 and 2, edge workgroups
-// for 1).
+// Batched Swendsen-Wang stage: 0 tiles (bonds, in-tile unions and the
+// tile-crossing links), 2 shift + recount; start: count+1 prefix sums of the
+// per-chain tiles.
 hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                            int stage, hipStream_t s);
 

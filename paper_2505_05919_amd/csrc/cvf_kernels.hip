@@ -117,8 +117,6 @@ __global__ void state_init_kernel(DevState* st, int64_t* slots, const DevTables*
         st->sw_done = 0;
         st->skip = 0;
         st->stop_at = INT64_MAX;
-        st->arrive = 0;
-        st->pad_ = 0;
     }
 }
 
@@ -146,12 +144,7 @@ __global__ __launch_bounds__(kBlock) void sigma_init_kernel(LatticeArgs a)
 // ---------------------------------------------------------------------------
 // Executed by one full wavefront (lanes 0..63); `term` is 40 doubles of LDS.
 // Every global load is issued before the first store, so the whole move
-// costs one memory round trip.  EXCH: the slots were filled by atomics of
-// the same launch (the last workgroup of a colour pass opens the next step),
-// so they are read and cleared with device-scope atomic exchanges, which see
-// every other workgroup's atomics wherever it ran; otherwise (a launch of its
-// own) plain loads and stores.
-template <bool EXCH = false>
+// costs one memory round trip.
 __device__ void volume_step(const VolArgs& a, double* term)
 {
     const int lane = threadIdx.x & 63;
@@ -160,10 +153,7 @@ __device__ void volume_step(const VolArgs& a, double* term)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int k = 0; k < kSlots / 64; ++k) {
-            int64_t* p = a.slots + j * kSlots + k * 64 + lane;
-            sl[j][k] = EXCH ? (int64_t)atomicExch((unsigned long long*)p, 0ull) : *p;
-        }
+        for (int k = 0; k < kSlots / 64; ++k) sl[j][k] = a.slots[j * kSlots + k * 64 + lane];
     const int64_t t_next = st->t_next, stop_at = st->stop_at;
     const int64_t hb0 = st->n_hb_raw, co0 = st->n_coop, macc0 = st->met_acc, matt0 = st->met_att;
     const int64_t vatt0 = st->vol_att, vacc0 = st->vol_acc;
@@ -177,12 +167,10 @@ __device__ void volume_step(const VolArgs& a, double* term)
         co += sl[1][k];
         ac += sl[2][k];
     }
-    if (!EXCH) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
-    }
+        for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
     const int64_t n_hb = hb0 + wave_sum64(hb);
     const int64_t n_co = co0 + wave_sum64(co);
     const int64_t m_acc = macc0 + wave_sum64(ac);
@@ -345,45 +333,36 @@ hipError_t launch_volume(const VolArgs& a, hipStream_t s)
 }
 
 template <int Q, bool R, bool LE>
-void launch_quad_r(const LatticeArgs& a, const VolArgs& v, int colour, int fold, dim3 grid, hipStream_t s)
+void launch_quad_r(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
 {
-    if (colour == 0) met_sweep4_kernel<Q, 0, R, LE><<<grid, 256, 0, s>>>(a, v, 0);
-    else met_sweep4_kernel<Q, 1, R, LE><<<grid, 256, 0, s>>>(a, v, fold);
+    if (colour == 0) met_sweep4_kernel<Q, 0, R, LE><<<grid, 256, 0, s>>>(a);
+    else met_sweep4_kernel<Q, 1, R, LE><<<grid, 256, 0, s>>>(a);
 }
 
 template <int Q>
-void launch_quad(const LatticeArgs& a, const VolArgs& v, int colour, int fold, dim3 grid, hipStream_t s)
+void launch_quad(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
 {
     if (a.quad == 2) {
-        if (a.met_le) launch_quad_r<Q, true, true>(a, v, colour, fold, grid, s);
-        else launch_quad_r<Q, true, false>(a, v, colour, fold, grid, s);
+        if (a.met_le) launch_quad_r<Q, true, true>(a, colour, grid, s);
+        else launch_quad_r<Q, true, false>(a, colour, grid, s);
     } else {
-        if (a.met_le) launch_quad_r<Q, false, true>(a, v, colour, fold, grid, s);
-        else launch_quad_r<Q, false, false>(a, v, colour, fold, grid, s);
+        if (a.met_le) launch_quad_r<Q, false, true>(a, colour, grid, s);
+        else launch_quad_r<Q, false, false>(a, colour, grid, s);
     }
-}
-
-hipError_t launch_met_colour_fold(const LatticeArgs& a, const VolArgs& v, int colour, int fold, hipStream_t s)
-{
-    if (a.quad) {
-        const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
-        switch (a.q) {
-        case 2: launch_quad<2>(a, v, colour, fold, grid, s); break;
-        case 3: launch_quad<3>(a, v, colour, fold, grid, s); break;
-        case 4: launch_quad<4>(a, v, colour, fold, grid, s); break;
-        case 5: launch_quad<5>(a, v, colour, fold, grid, s); break;
-        default: launch_quad<6>(a, v, colour, fold, grid, s); break;
-        }
-        return hipGetLastError();
-    }
-    return launch_met_colour(a, colour, s);       // column pairs: no fold
 }
 
 hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
 {
     if (a.quad) {
-        VolArgs none{};
-        return launch_met_colour_fold(a, none, colour, 0, s);
+        const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
+        switch (a.q) {
+        case 2: launch_quad<2>(a, colour, grid, s); break;
+        case 3: launch_quad<3>(a, colour, grid, s); break;
+        case 4: launch_quad<4>(a, colour, grid, s); break;
+        case 5: launch_quad<5>(a, colour, grid, s); break;
+        default: launch_quad<6>(a, colour, grid, s); break;
+        }
+        return hipGetLastError();
     }
     const dim3 grid((a.L / 2 + 63) / 64, a.row_blocks), block(256);
     switch (a.q) {
@@ -513,31 +492,40 @@ hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sw_union_edges(const LatticeArgs& a, hipStream_t s)
+__global__ void sw_counters_init_kernel(uint32_t* ecnt, uint32_t n)
 {
-    const uint32_t ncx = (a.L + kTW - 1) / kTW, ncy = (a.L + kTH - 1) / kTH;
-    const uint64_t n = (uint64_t)(ncx + ncy) * a.L;
-    sw_union_edges_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, ncx, ncy);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) ecnt[i] = 0;
+}
+
+hipError_t launch_sw_counters_init(const LatticeArgs& a, hipStream_t s)
+{
+    const uint32_t n = 2 * ((a.L + kTW - 1) / kTW) * ((a.L + kTH - 1) / kTH);
+    sw_counters_init_kernel<<<grid_for(n), kBlock, 0, s>>>(a.ecnt, n);
     return hipGetLastError();
 }
 
 template <int Q>
 void launch_batch_q(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total, int colour,
-                    hipStream_t s)
+                    int le, hipStream_t s)
 {
-    if (colour == 0) met_batch_kernel<Q, 0><<<total, 256, 0, s>>>(ent, start, count);
-    else met_batch_kernel<Q, 1><<<total, 256, 0, s>>>(ent, start, count);
+    if (le) {
+        if (colour == 0) met_batch_kernel<Q, 0, true><<<total, 256, 0, s>>>(ent, start, count);
+        else met_batch_kernel<Q, 1, true><<<total, 256, 0, s>>>(ent, start, count);
+    } else {
+        if (colour == 0) met_batch_kernel<Q, 0, false><<<total, 256, 0, s>>>(ent, start, count);
+        else met_batch_kernel<Q, 1, false><<<total, 256, 0, s>>>(ent, start, count);
+    }
 }
 
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
-                            int q, int colour, hipStream_t s)
+                            int q, int colour, int le, hipStream_t s)
 {
     switch (q) {
-    case 2: launch_batch_q<2>(ent, start, count, total_blocks, colour, s); break;
-    case 3: launch_batch_q<3>(ent, start, count, total_blocks, colour, s); break;
-    case 4: launch_batch_q<4>(ent, start, count, total_blocks, colour, s); break;
-    case 5: launch_batch_q<5>(ent, start, count, total_blocks, colour, s); break;
-    default: launch_batch_q<6>(ent, start, count, total_blocks, colour, s); break;
+    case 2: launch_batch_q<2>(ent, start, count, total_blocks, colour, le, s); break;
+    case 3: launch_batch_q<3>(ent, start, count, total_blocks, colour, le, s); break;
+    case 4: launch_batch_q<4>(ent, start, count, total_blocks, colour, le, s); break;
+    case 5: launch_batch_q<5>(ent, start, count, total_blocks, colour, le, s); break;
+    default: launch_batch_q<6>(ent, start, count, total_blocks, colour, le, s); break;
     }
     return hipGetLastError();
 }
@@ -553,15 +541,14 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_
 {
     if (total_blocks == 0) return hipSuccess;
     if (stage == 0) sw_tile_batch_kernel<<<total_blocks, kTT, 0, s>>>(ent, start, count);
-    else if (stage == 1) sw_edge_batch_kernel<<<total_blocks, 256, 0, s>>>(ent, start, count);
     else sw_flip_batch_kernel<<<total_blocks, kTT, 0, s>>>(ent, start, count);
     return hipGetLastError();
 }
 
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, const VolArgs& v, int fold, hipStream_t s)
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a, v, fold);
+    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ __device__ __forceinline__ CellBytes met_load(const LatticeArgs& a, __amdgpu_buf
 }
 
 // Update the four arms of the cell (x, y) from its loaded bytes and store them.
-template <int Q, bool VROW = false>
+template <int Q, bool VROW = false, bool LE = false>
 __device__ __forceinline__ void met_cell(const LatticeArgs& a, __amdgpu_buffer_rsrc_t rs, const uint2* tbl,
                                          uint32_t t, uint32_t y, uint32_t x, const CellBytes& b, uint32_t& wsum)
 {
@@ -115,11 +115,11 @@ __device__ __forceinline__ void met_cell(const LatticeArgs& a, __amdgpu_buffer_r
     const uint4 wa = philox(c, t, 0u, kStreamMet, a.key0, a.key1);
     const uint4 wb = philox(c, t, 1u, kStreamMet, a.key0, a.key1);
     const uint32_t p23 = (1u << s2) + (1u << s3);
-    met_arm<Q>(s0, p23 + (1u << s1) + (8u << f0), wa.x, wa.y, tbl, wsum);
-    met_arm<Q>(s1, p23 + (1u << s0) + (8u << f1), wa.z, wa.w, tbl, wsum);
+    met_arm<Q, LE>(s0, p23 + (1u << s1) + (8u << f0), wa.x, wa.y, tbl, wsum);
+    met_arm<Q, LE>(s1, p23 + (1u << s0) + (8u << f1), wa.z, wa.w, tbl, wsum);
     const uint32_t p01 = (1u << s0) + (1u << s1);
-    met_arm<Q>(s2, p01 + (1u << s3) + (8u << f2), wb.x, wb.y, tbl, wsum);
-    met_arm<Q>(s3, p01 + (1u << s2) + (8u << f3), wb.z, wb.w, tbl, wsum);
+    met_arm<Q, LE>(s2, p01 + (1u << s3) + (8u << f2), wb.x, wb.y, tbl, wsum);
+    met_arm<Q, LE>(s3, p01 + (1u << s2) + (8u << f3), wb.z, wb.w, tbl, wsum);
     st8(rs, s0 >> 2, RS::v(x, o0), RS::s(0, o0));
     st8(rs, s1 >> 2, RS::v(x, o0), RS::s(N, o0));
     st8(rs, s2 >> 2, RS::v(x, o0), RS::s(2 * N, o0));
@@ -285,23 +285,6 @@ __device__ __forceinline__ void met_quad(const LatticeArgs& a, __amdgpu_buffer_r
     st32r<R, DMIS>(rs, put2<B1, B2>(q.d3, a3, b3), xv, RS::s(3 * N, o0), ragged);
 }
 
-__device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int theta)
-{
-    const int tid = threadIdx.x;
-    if (tid < 32) {
-        const int dd = tid - 16;                          // dc + 8 dh
-        const int dh = (dd + 4) >> 3;
-        const int dc = dd - 8 * dh;
-        uint2 e = make_uint2(0u, 0u);
-        if (dd >= -11 && dd <= 11 && dc >= -3 && dc <= 3) {
-            e.x = a.tab->met[theta][(dh + 1) * 7 + dc + 3];
-            e.y = (uint32_t)(dc + (dh << 10) + (1 << 20));
-        }
-        tbl[tid] = e;
-    }
-    __syncthreads();
-}
-
 // Entry i (0..63) of the two-theta table: theta = i / 32, index d + 16 with
 // d = dc + 8 dh; entries that no (dc, dh) reaches hold 0.
 template <bool LE>
@@ -317,6 +300,14 @@ __device__ __forceinline__ uint2 met_table_entry(const LatticeArgs& a, int i)
         e.y = (uint32_t)(dc + (dh << 10) + (1 << 20));
     }
     return e;
+}
+
+// The 32 entries of one theta's table in LDS (index d + 16); ends with a barrier.
+template <bool LE = false>
+__device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int theta)
+{
+    if (threadIdx.x < 32) tbl[threadIdx.x] = met_table_entry<LE>(a, 32 * theta + (int)threadIdx.x);
+    __syncthreads();
 }
 
 __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32_t slot)
@@ -364,16 +355,10 @@ struct ProgressPrio {
 // chain state, so the table entries of both theta values and the first row
 // are requested before the state (skip flag, theta, step) is read, and the
 // first wait covers all three at once.
-//
-// fold (colour 1 only): the workgroup that finishes last -- a counter in the
-// chain state, incremented by every workgroup after its counter atomics have
-// completed -- folds the slots and performs the next step's volume move,
-// which otherwise is a launch of its own between two sweeps.
 template <int Q, int KAPPA, bool R, bool LE>
-__global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a, VolArgs va, int fold)
+__global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a)
 {
     __shared__ uint2 tbl[64];
-    __shared__ double term[40];
     const uint32_t tid = threadIdx.x;
     uint2 e = make_uint2(0u, 0u);
     if (tid < 64) e = met_table_entry<LE>(a, (int)tid);
@@ -412,17 +397,6 @@ __global__ __launch_bounds__(256) void met_sweep4_kernel(LatticeArgs a, VolArgs 
         }
     }
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
-    // The workgroup's counter atomics were issued by wave 0; once they are
-    // performed (release fence) lane 0 counts the workgroup as finished.
-    if (!fold || tid >= 64) return;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t total = gridDim.x * gridDim.y;
-    uint32_t prev = 0;
-    if (tid == 0) prev = atomicInc(&a.st->arrive, total - 1);     // wraps to 0 for the next launch
-    prev = (uint32_t)__shfl((int)prev, 0, 64);
-    if (prev != total - 1) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    volume_step<true>(va, term);
 }
 
 // Byte-lane variant (any even L): lane i owns the column pair (2i, 2i+1).
@@ -492,7 +466,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // ---------------------------------------------------------------------------
 // Batches are mostly small lattices: the 8-wavefront occupancy measured
 // faster than the uncapped register budget.
-template <int Q, int KAPPA>
+template <int Q, int KAPPA, bool LE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void met_batch_kernel(
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ start, uint32_t count)
 {
@@ -529,20 +503,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         at(first, y, x4, xl, xr);
         QuadBytes cur = {};
         if (first < units) cur = met_load4<PE, false, false, true>(a, rs, y, x4, x4 + 2, xl, xr);
-        met_table(a, tbl, theta);
+        met_table<LE>(a, tbl, theta);
         for (uint32_t i = 0; i < K; ++i) {
             const uint32_t u = first + 64 * i;
             const bool act = u < units;
             QuadBytes odd = {};
             if (act) {
                 odd = met_load4<PO, false, true, true>(a, rs, y + 1, x4, x4 + 2, xl, xr);
-                met_quad<Q, PE, false, false, false, true>(a, rs, tbl, t, y, x4, cur, wsum, false);
+                met_quad<Q, PE, false, false, LE, true>(a, rs, tbl, t, y, x4, cur, wsum, false);
             }
             const uint32_t un = u + 64;
             uint32_t yn, x4n, xln, xrn;
             at(un, yn, x4n, xln, xrn);
             if (i + 1 < K && un < units) cur = met_load4<PE, false, false, true>(a, rs, yn, x4n, x4n + 2, xln, xrn);
-            if (act) met_quad<Q, PO, false, true, false, true>(a, rs, tbl, t, y + 1, x4, odd, wsum, false);
+            if (act) met_quad<Q, PO, false, true, LE, true>(a, rs, tbl, t, y + 1, x4, odd, wsum, false);
             y = yn;
             x4 = x4n;
             xl = xln;
@@ -563,7 +537,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             nb(2 * pr + KAPPA, xp, xm);
             cur = met_load<true>(a, rs, y, 2 * pr + KAPPA, xp, xm);
         }
-        met_table(a, tbl, theta);
+        met_table<LE>(a, tbl, theta);
         for (uint32_t i = 0; i < K; ++i) {
             const uint32_t u = first + 64 * i;
             const bool act = u < units;
@@ -572,7 +546,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             if (act) {
                 nb(xB, xp, xm);
                 odd = met_load<true>(a, rs, y + 1, xB, xp, xm);
-                met_cell<Q, true>(a, rs, tbl, t, y, xA, cur, wsum);
+                met_cell<Q, true, LE>(a, rs, tbl, t, y, xA, cur, wsum);
             }
             const uint32_t un = u + 64;
             uint32_t yn, prn;
@@ -581,7 +555,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                 nb(2 * prn + KAPPA, xp, xm);
                 cur = met_load<true>(a, rs, yn, 2 * prn + KAPPA, xp, xm);
             }
-            if (act) met_cell<Q, true>(a, rs, tbl, t, y + 1, xB, odd, wsum);
+            if (act) met_cell<Q, true, LE>(a, rs, tbl, t, y + 1, xB, odd, wsum);
             y = yn;
             pr = prn;
         }

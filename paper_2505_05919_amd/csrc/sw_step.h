@@ -177,8 +177,9 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 //                         components holding one (-> themselves); the old
 //                         sigma facing the right and bottom edges; every
 //                         bond index's tile-local root (uint16, with the
-//                         border flag of its component).
-//  sw_union_edges_kernel  the tile-crossing links (global union-find).
+//                         border flag of its component); then the tile-
+//                         crossing links, each united (global union-find)
+//                         by the later of the two tiles it joins.
 //  sw_flip_tile_kernel    one shift per tile-local component (its cluster
 //                         minimum comes from the global labels if the
 //                         component touches the border, else it is the
@@ -188,7 +189,6 @@ __device__ __forceinline__ uint32_t find_root(const uint32_t* label, uint32_t x)
 //  sw_labels_kernel       the full label array, on request.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kIdx = 4 * kTC - 1;  // local index bits of an LDS label
-constexpr uint32_t kBorderIdx = 2 * (kTW + kTH);   // border bond indices of a tile
 constexpr uint32_t kBorder = 0x8000u;  // flag on the root of a component that holds a border bond index
 static_assert(4 * kTC <= kBorder, "local bond indices must stay below the border flag");
 static_assert((4 * kTC & (4 * kTC - 1)) == 0, "kIdx is a bit mask");
@@ -343,15 +343,33 @@ __device__ __forceinline__ void tile_masks(const LatticeArgs& a, const TileGeom&
     }
 }
 
-// lut: 64 bytes, lab: 4 kTC words of LDS.
-__device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeom& g, uint8_t* lut, uint32_t* lab)
+// Lock-free union of the clusters with roots pu and pv (minimum index wins):
+// atomicMin points the larger at the smaller and returns its previous
+// parent p; p == the larger means it was a root and the union is done,
+// otherwise the pair (smaller, p) is united next, so no connection is lost.
+// The larger element of the pair strictly decreases, so the loop ends.
+__device__ __forceinline__ void unite_global(uint32_t* label, uint32_t pu, uint32_t pv)
+{
+    while (pu != pv) {
+        if (pu > pv) {
+            const uint32_t tmp = pu;
+            pu = pv;
+            pv = tmp;
+        }
+        const uint32_t old = atomicMin(label + pv, pu);
+        if (old == pv) return;
+        pv = old;
+    }
+}
+
+// lut: 64 bytes, lab: 4 kTC words, act: kEdgeBytes bytes of LDS.
+__device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeom& g, uint8_t* lut, uint32_t* lab,
+                                             uint8_t* act)
 {
     // Waves of a SIMD issue oldest first; a workgroup that has finished its
     // bonds yields to those still computing theirs, so all tiles reach the
     // latency-bound union phases together (priority 3, 2, 0 by phase).
     __builtin_amdgcn_s_setprio(3);
-    build_incell_lut(lut);
-    const SwBondCtx k = sw_ctx(a);
     const uint32_t L = a.L, N = a.N;
     uint8_t* edge = a.edge + (size_t)g.id * kEdgeBytes;
     // cell i of a thread: tile column lane, tile row wave + W i (wave-uniform),
@@ -361,21 +379,40 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     const uint32_t x = g.x0 + lane;
     const uint32_t vx = col_in ? x : 0u, vxp = col_in ? ((x + 1 == L) ? 0u : x + 1) : 0u;
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N), rm = buf_rsrc(a.mask, N);
+    // the bond indices of the thread's cells and their facing arms first:
+    // they do not depend on the chain state, whose loads then overlap them
+    uint32_t sv[kTC / kTT][6];
+#pragma unroll
+    for (uint32_t i = 0; i < kTC / kTT; ++i) {
+        const uint32_t ly = wave + (kTT / 64) * i;
+        const uint32_t y = g.y0 + (ly < g.h ? ly : 0), row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
+        sv[i][0] = ld8(rs, vx, row);
+        sv[i][1] = ld8(rs, vx, N + row);
+        sv[i][2] = ld8(rs, vx, 2 * N + row);
+        sv[i][3] = ld8(rs, vx, 3 * N + row);
+        sv[i][4] = ld8(rs, vxp, N + row);
+        sv[i][5] = ld8(rs, vx, 3 * N + rowp);
+    }
+    if (a.st->skip) return;                    // step limit reached (uniform, before any barrier)
+    build_incell_lut(lut);
+    const SwBondCtx k = sw_ctx(a);
     uint32_t mk[kTC / kTT];
 #pragma unroll
     for (uint32_t i = 0; i < kTC / kTT; ++i) {
         const uint32_t ly = wave + (kTT / 64) * i;
         uint32_t m = 0;
-        if (ly < g.h) {
-            const uint32_t y = g.y0 + ly, row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
-            const uint32_t s0 = ld8(rs, vx, row), s1 = ld8(rs, vx, N + row), s2 = ld8(rs, vx, 2 * N + row),
-                           s3 = ld8(rs, vx, 3 * N + row);
-            const uint32_t f0 = ld8(rs, vxp, N + row), f2 = ld8(rs, vx, 3 * N + rowp);
-            if (col_in) {
-                m = sw_bond_bits(a, k, x + row, s0, s1, s2, s3, f0, f2);
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)m, rm, (int)vx, (int)row, 0);
-                if (lane == g.w - 1) edge[ly] = (uint8_t)f0;
-                if (ly == g.h - 1) edge[kTH + lane] = (uint8_t)f2;
+        if (ly < g.h && col_in) {
+            const uint32_t y = g.y0 + ly, row = y * L;
+            const uint32_t f0 = sv[i][4], f2 = sv[i][5];
+            m = sw_bond_bits(a, k, x + row, sv[i][0], sv[i][1], sv[i][2], sv[i][3], f0, f2);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)m, rm, (int)vx, (int)row, 0);
+            if (lane == g.w - 1) {
+                edge[ly] = (uint8_t)f0;
+                act[ly] = (uint8_t)(m & 1u);               // the +x link leaving the tile
+            }
+            if (ly == g.h - 1) {
+                edge[kTH + lane] = (uint8_t)f2;
+                act[kTH + lane] = (uint8_t)((m >> 1) & 1u);  // the +y link leaving the tile
             }
         }
         mk[i] = m;
@@ -416,77 +453,94 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
                 const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lroot + (size_t)p * N, 2 * N);
                 __builtin_amdgcn_raw_buffer_store_b16((uint16_t)e[j], rl, (int)voff, (int)(2 * (g.y0 + ly) * L), 0);
                 const uint32_t v = p * kTC + ly * kTW + lane;
-                if (r[j] == v && (e[j] & kBorder)) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, v);
+                if (r[j] == v && (e[j] & kBorder)) {
+                    // a root other tiles' unions may reach this step: written
+                    // through to the device-coherent level (see below)
+                    const uint32_t gv = tile_global(g, L, N, v);
+                    __hip_atomic_store(a.label + gv, gv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
     }
-    if (threadIdx.x < 2 * (kTW + kTH)) {
-        const uint32_t v = border_local(g, threadIdx.x);
-        if (v < 4 * kTC) a.label[tile_global(g, L, N, v)] = tile_global(g, L, N, find_root_lds(lab, v));
+    // Tile-crossing links.  Every border bond index gets the global label of
+    // its root (the flip follows these chains), and the tile publishes one
+    // exchange word per border bond index: the global root of its component,
+    // for the ends in the last column and row only if the link leaving there
+    // is active (kNoLink otherwise).  Each tile edge has an arrival counter
+    // that the two tiles beside it increment once per step (it wraps back to
+    // 0); the tile that arrives second unites that edge's active links with
+    // the first tile's words.  No tile ever waits for another.
+    // Everything one tile reads of another's within this launch -- the
+    // exchange words and the label entries the unions' atomicMin acts on --
+    // is written and read only with device-scope atomic stores, loads and
+    // read-modify-writes, which all act at the device-coherent level (across
+    // the XCDs' separate L2 caches); no plain store touches those entries in
+    // this launch.  The barrier below waits for this tile's stores to
+    // complete before its counter increments are issued, and the other
+    // tile's words are read only after its increment was seen.  (Device-scope
+    // fences would do the same by writing back and invalidating whole L2
+    // caches, which measured four times slower.)
+    uint32_t* xw = a.xchg + (size_t)g.id * kBorderIdx;
+    if (threadIdx.x < kBorderIdx) {
+        const uint32_t b = threadIdx.x;
+        const uint32_t v = border_local(g, b);
+        uint32_t w = kNoLink;
+        if (v < 4 * kTC) {
+            const uint32_t gr = tile_global(g, L, N, find_root_lds(lab, v));
+            // device-scope store: other tiles' atomicMin may act on this
+            // entry (when v is its own root) before the launch ends, and a
+            // plain store's dirty L2 line written back later would undo it
+            __hip_atomic_store(a.label + tile_global(g, L, N, v), gr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool on = true;
+            if (b < kTH) on = act[b] != 0;
+            else if (b >= 2 * kTH && b < 2 * kTH + kTW) on = act[kTH + (b - 2 * kTH)] != 0;
+            w = on ? gr : kNoLink;
+        }
+        __hip_atomic_store(xw + b, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(0);            // this wave's stores are complete ...
+    __syncthreads();                          // ... and so are every wave's, before any increment
+    const uint32_t ncx = (L + kTW - 1) / kTW, ncy = (L + kTH - 1) / kTH;
+    const uint32_t bx = g.x0 / kTW, by = g.y0 / kTH;
+    const uint32_t right = (bx + 1 == ncx ? 0 : bx + 1) + by * ncx, left = (bx == 0 ? ncx - 1 : bx - 1) + by * ncx;
+    const uint32_t down = bx + (by + 1 == ncy ? 0 : by + 1) * ncx, up = bx + (by == 0 ? ncy - 1 : by - 1) * ncx;
+    uint8_t* second = lut;                    // the in-cell table is dead: four flags
+    if (threadIdx.x < 4) {
+        // edges: 0 right (counter 2 id), 1 bottom (2 id + 1), 2 left (the left
+        // tile's right edge), 3 top (the upper tile's bottom edge)
+        const uint32_t e = threadIdx.x;
+        const uint32_t c = e == 0 ? 2 * g.id : e == 1 ? 2 * g.id + 1 : e == 2 ? 2 * left : 2 * up + 1;
+        second[e] = atomicInc(a.ecnt + c, 1u) == 1u ? 1 : 0;
+    }
+    __syncthreads();
+    if (!(second[0] | second[1] | second[2] | second[3])) return;
+    auto word = [](const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    const uint32_t e = threadIdx.x >> 6, pos = threadIdx.x & 63;
+    if (e < 4 && second[e]) {
+        uint32_t pu = kNoLink, pv = kNoLink;  // pu: the word that carries the link's activity
+        if (e == 0 && pos < g.h) {
+            pu = word(xw + pos);
+            pv = word(a.xchg + (size_t)right * kBorderIdx + kTH + pos);
+        } else if (e == 2 && pos < g.h) {
+            pu = word(a.xchg + (size_t)left * kBorderIdx + pos);
+            pv = word(xw + kTH + pos);
+        } else if (e == 1 && pos < g.w) {
+            pu = word(xw + 2 * kTH + pos);
+            pv = word(a.xchg + (size_t)down * kBorderIdx + 2 * kTH + kTW + pos);
+        } else if (e == 3 && pos < g.w) {
+            pu = word(a.xchg + (size_t)up * kBorderIdx + 2 * kTH + pos);
+            pv = word(xw + 2 * kTH + kTW + pos);
+        }
+        if (pu != kNoLink) unite_global(a.label, pu, pv);
     }
 }
 
 __global__ __launch_bounds__(kTT) void sw_tile_kernel(LatticeArgs a)
 {
-    if (a.st->skip) return;
     __shared__ uint8_t lut[64];
     __shared__ uint32_t lab[4 * kTC];
-    sw_tile_body(a, grid_tile(a.L), lut, lab);
-}
-
-// Covalent links that leave their tile: +x links of the last column of each
-// tile (and of column L-1, which wraps), +y links of the last row of each
-// tile (and of row L-1).  Thread i < L * ncx handles column-edge cells,
-// the rest row-edge cells.  Both ends are border bond indices, whose labels
-// the tile kernel wrote; they are read together with the link mask.
-__device__ __forceinline__ void sw_edge_body(const LatticeArgs& a, uint32_t i, uint32_t ncx, uint32_t ncy)
-{
-    const uint32_t L = a.L, N = a.N;
-    const uint32_t nx = ncx * L, ny = ncy * L;
-    if (i >= nx + ny) return;
-    uint32_t c, u, v, bit;
-    if (i < nx) {
-        const uint32_t y = i / ncx, j = i - y * ncx;
-        const uint32_t x = min(j * kTW + kTW - 1, L - 1);     // last column of tile j (clamped: x = L-1)
-        c = x + y * L;
-        u = c;
-        v = N + ((x + 1 == L) ? 0 : x + 1) + y * L;
-        bit = 1;
-    } else {
-        const uint32_t r = i - nx;
-        const uint32_t x = r / ncy, j = r - x * ncy;
-        const uint32_t y = min(j * kTH + kTH - 1, L - 1);
-        c = x + y * L;
-        u = 2 * N + c;
-        v = 3 * N + x + ((y + 1 == L) ? 0 : y + 1) * L;
-        bit = 2;
-    }
-    const uint32_t m = a.mask[c];
-    uint32_t pu = a.label[u], pv = a.label[v];
-    if (!(m & bit)) return;
-    // Lock-free union by minimum index without root finding: both ends start
-    // from their tile roots (usually still roots), and atomicMin points the
-    // larger node of the pair at the smaller one.  It returns the node's
-    // previous parent p: p == node means it was a root and the union is done;
-    // otherwise the node now points at min(p, smaller) and the pair (smaller,
-    // p) is united next, so no connection is lost.  The larger element of the
-    // pair strictly decreases, so the loop ends.
-    while (pu != pv) {
-        if (pu > pv) {
-            const uint32_t tmp = pu;
-            pu = pv;
-            pv = tmp;
-        }
-        const uint32_t old = atomicMin(a.label + pv, pu);
-        if (old == pv) return;
-        pv = old;
-    }
-}
-
-__global__ __launch_bounds__(256) void sw_union_edges_kernel(LatticeArgs a, uint32_t ncx, uint32_t ncy)
-{
-    if (a.st->skip) return;
-    sw_edge_body(a, blockIdx.x * 256 + threadIdx.x, ncx, ncy);
+    __shared__ uint8_t act[kEdgeBytes];
+    sw_tile_body(a, grid_tile(a.L), lut, lab, act);
 }
 
 // LDS of the flip: the compacted roots of the interior components, whose
@@ -531,8 +585,6 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
         lds.nrootb = 0;
     }
     const uint32_t L = a.L, N = a.N, q = a.q;
-    const uint32_t t = a.st->t_cur;
-    if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
     // entry i: plane i / 4, tile row ent_row(wave, i), column lane
     const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool col_in = lane < g.w;
@@ -552,6 +604,10 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
             if (col_in) lr[i] = l;
         }
     }
+    // the loads above do not depend on the chain state; read it now
+    if (a.st->skip) return;                   // step limit reached (uniform, before any barrier)
+    const uint32_t t = a.st->t_cur;
+    if (g.id == 0 && threadIdx.x == 0) a.st->sw_done = 1;
 #pragma unroll
     for (uint32_t i = 0; i < 4 * kTC / kTT; ++i) lds.osg[ent_local(wave, lane, i)] = (uint8_t)os[i];
     // the 16-bit local roots, two per register for the rest of the kernel
@@ -680,26 +736,10 @@ __device__ __forceinline__ void sw_flip_body(const LatticeArgs& a, const TileGeo
     block_add<2, kTT>(v2, a.slots + (g.id & (kSlots - 1)), kSlots);
 }
 
-// fold: the workgroup that finishes last (a counter in the chain state,
-// incremented once the workgroup's counter atomics are performed) folds the
-// slots -- the recount of the new configuration -- and opens the next step
-// with its volume move, which otherwise is a launch of its own.
-__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(
-    LatticeArgs a, VolArgs va, int fold)
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_tile_kernel(LatticeArgs a)
 {
-    if (a.st->skip) return;
     __shared__ FlipLds lds;
-    __shared__ double term[40];
     sw_flip_body(a, grid_tile(a.L), lds);
-    if (!fold || threadIdx.x >= 64) return;                // block_add's atomics are wave 0's
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t total = gridDim.x * gridDim.y;
-    uint32_t prev = 0;
-    if (threadIdx.x == 0) prev = atomicInc(&a.st->arrive, total - 1);
-    prev = (uint32_t)__shfl((int)prev, 0, 64);
-    if (prev != total - 1) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    volume_step<true>(va, term);
 }
 
 // label[idx] = the minimum of idx's cluster, for every bond index; written
@@ -755,20 +795,10 @@ __global__ __launch_bounds__(kTT) void sw_tile_batch_kernel(const BatchEntry* __
 {
     __shared__ uint8_t lut[64];
     __shared__ uint32_t lab[4 * kTC];
+    __shared__ uint8_t act[kEdgeBytes];
     const uint32_t c = batch_chain(tstart, count, blockIdx.x);
     const LatticeArgs a = ent[c].la;
-    if (a.st->skip) return;
-    sw_tile_body(a, batch_tile(a, blockIdx.x - tstart[c]), lut, lab);
-}
-
-__global__ __launch_bounds__(256) void sw_edge_batch_kernel(const BatchEntry* __restrict__ ent,
-                                                            const uint32_t* __restrict__ estart, uint32_t count)
-{
-    const uint32_t c = batch_chain(estart, count, blockIdx.x);
-    const LatticeArgs a = ent[c].la;
-    if (a.st->skip) return;
-    const uint32_t ncx = (a.L + kTW - 1) / kTW, ncy = (a.L + kTH - 1) / kTH;
-    sw_edge_body(a, (blockIdx.x - estart[c]) * 256 + threadIdx.x, ncx, ncy);
+    sw_tile_body(a, batch_tile(a, blockIdx.x - tstart[c]), lut, lab, act);
 }
 
 __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_batch_kernel(
@@ -777,6 +807,5 @@ __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     __shared__ FlipLds lds;
     const uint32_t c = batch_chain(tstart, count, blockIdx.x);
     const LatticeArgs a = ent[c].la;
-    if (a.st->skip) return;
     sw_flip_body(a, batch_tile(a, blockIdx.x - tstart[c]), lds);
 }

@@ -50,9 +50,10 @@ def test_workspace_bytes(cvf):
     N = 1414 * 1414
     tiles = ((1414 + 63) // 64) * ((1414 + 31) // 32)
     assert met < 8192
-    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell, 96 B per 64x32 tile
-    assert both - met >= 25 * N + 96 * tiles
-    assert both - met < 25 * N + 96 * tiles + 1024
+    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell; per 64x32
+    # tile 96 edge bytes, 192 exchange words and 2 edge counters (872 B)
+    assert both - met >= 25 * N + 872 * tiles
+    assert both - met < 25 * N + 872 * tiles + 6 * 256
 
 
 @pytest.mark.parametrize("field,value", [("L", 1), ("L", 0), ("L", 32768), ("q", 1), ("q", 7),

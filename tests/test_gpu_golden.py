@@ -1,13 +1,18 @@
-"""Full-size GPU parity against stored oracle trajectories.
+"""Full-length GPU parity against stored oracle results.
 
-tests/golden/trajectories.json holds, for the temperature scan (L = 1024,
-five temperatures), the pressure scan on the headline lattice (L = 4096
-Metropolis, L = 1414 Swendsen-Wang, three pressures) and a small SW scan,
-the SHA-256 of sigma, every integer counter and v at checkpoints, written by
-tests/golden/make_golden.py from the oracle alone.  The library replays each
-trajectory in the launch configuration the benchmark times: single chains
-with default launches, and the Metropolis cases again as one batch with the
-autotuned row count and hipGraph-replayed sweep blocks.
+tests/golden/ holds, written by tests/golden/make_golden.py from the oracle
+alone:
+* trajectories.json -- the SHA-256 of sigma, every integer counter and v at
+  checkpoints up to each configuration's stated length: the temperature scan
+  (L = 1024, 10^4 Metropolis sweeps; L = 256, 10^3 Swendsen-Wang steps; five
+  temperatures each) and the pressure scan on the paper-scale lattices
+  (L = 4096 Metropolis, L = 1414 Swendsen-Wang, 10^3 steps, three pressures);
+* c4_replicas.json -- the same at 100 and 1000 sweeps for every one of the
+  256 batched replicas (L log-uniform in 64..512, 16 x 16 (T, P) grid).
+The library replays each trajectory in the launch configurations the
+benchmark times: single chains, the scans as batches (autotuned rows,
+hipGraph-replayed sweep blocks for Metropolis), and the 256 replicas as one
+batch with 100-sweep graph blocks.
 """
 import hashlib
 import json
@@ -19,8 +24,18 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-with open(os.path.join(HERE, "golden", "trajectories.json")) as f:
-    GOLD = json.load(f)["cases"]
+
+
+def _load(name, key):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)[key]
+
+
+GOLD = _load("trajectories.json", "cases")
+C4 = _load("c4_replicas.json", "replicas")
 INT_KEYS = ("n_hb_raw", "n_coop", "count", "met_accepted", "vol_accepted")
 
 
@@ -49,6 +64,7 @@ def check(ch, cp, ctx):
     o = ch.obs()
     for k in INT_KEYS:
         assert o[k] == cp[k], (ctx, k, o[k], cp[k])
+    assert o["step"] == cp["step"], ctx
     assert o["consistent"] == 1, ctx
     assert o["v"] == pytest.approx(cp["v"], rel=1e-12), (ctx, o["v"], cp["v"])
     assert hashlib.sha256(ch.sigma.cpu().numpy().tobytes()).hexdigest() == cp["sha256"], ctx
@@ -68,30 +84,78 @@ def test_golden_single(cvf, name):
     ch.close()
 
 
-@pytest.mark.parametrize("scan", ["c2a", "c3a"])
+@pytest.mark.parametrize("scan", ["c2a", "c3a", "c2b", "c3b"])
 def test_golden_batched(cvf, scan):
-    """A scan's Metropolis chains as one batch: autotuned rows, graph blocks."""
-    names = sorted(n for n in GOLD if n.startswith(scan) and GOLD[n]["algo"] == "met")
-    say(f"case golden batch {scan}: {names}")
-    tune = [make(cvf, GOLD[n]) for n in names]       # the autotuner advances its chains
-    tb = cvf.Batch(tune)
-    rows = tb.autotune(2)
-    tb.close()
-    for ch in tune:
-        ch.close()
+    """A scan's chains as one batch: Metropolis with the autotuned rows and
+    graph-replayed sweep blocks, Swendsen-Wang with one launch per stage."""
+    names = sorted(n for n in GOLD if n.startswith(scan))
+    algo = GOLD[names[0]]["algo"]
+    say(f"case golden batch {scan} ({algo}): {names}")
+    rows = 0
+    if algo == "met":
+        tune = [make(cvf, GOLD[n]) for n in names]       # the autotuner advances its chains
+        tb = cvf.Batch(tune)
+        rows = tb.autotune(2)
+        tb.close()
+        for ch in tune:
+            ch.close()
     chains = [make(cvf, GOLD[n]) for n in names]
     b = cvf.Batch(chains)
-    b.set_rows(rows)
+    if rows:
+        b.set_rows(rows)
     done = 0
     cps = GOLD[names[0]]["checkpoints"]
     for i, cp in enumerate(cps):
         n = cp["step"] - done
-        blk = 5 if n % 5 == 0 else 0
-        b.metropolis(n, graph_block=blk)
+        if algo == "met":
+            blk = 10 if n % 10 == 0 else 0
+            b.metropolis(n, graph_block=blk)
+        else:
+            b.sw(n)
         done = cp["step"]
         for nm, ch in zip(names, chains):
             assert GOLD[nm]["checkpoints"][i]["step"] == done
             check(ch, GOLD[nm]["checkpoints"][i], f"batch {nm} step {done} rows {rows}")
     b.close()
     for ch in chains:
+        ch.close()
+
+
+def test_c4_replicas_batched_against_oracle(cvf):
+    """All 256 replicas as one batch, autotuned rows, 100-sweep graph blocks,
+    1000 sweeps: every replica equals the stored oracle result at 100 and at
+    1000 sweeps."""
+    from paper_2505_05919_amd.workloads import c4_jobs
+    if not C4:
+        pytest.skip("tests/golden/c4_replicas.json not written yet")
+    jobs = c4_jobs()
+    say("case golden c4: 256 replicas, 1000 sweeps")
+
+    def chains():
+        out = []
+        for j in jobs:
+            p = cvf.cvf_params_from_si(j.T, j.P, L=j.L, seed=j.seed)
+            out.append(cvf.Chain(p, cvf.CVF_ALGO_METROPOLIS))
+        return out
+    tune = chains()
+    tb = cvf.Batch(tune)
+    rows = tb.autotune(2)
+    tb.close()
+    for ch in tune:
+        ch.close()
+    chs = chains()
+    for k, j in enumerate(jobs):
+        g = C4[f"r{k:03d}"]
+        assert (g["L"], g["seed"]) == (j.L, j.seed)
+    b = cvf.Batch(chs)
+    b.set_rows(rows)
+    done = 0
+    for i in range(2):
+        step = C4["r000"]["checkpoints"][i]["step"]
+        b.metropolis(step - done, graph_block=100)
+        done = step
+        for k, ch in enumerate(chs):
+            check(ch, C4[f"r{k:03d}"]["checkpoints"][i], f"c4 replica {k} L={jobs[k].L} step {step} rows {rows}")
+    b.close()
+    for ch in chs:
         ch.close()

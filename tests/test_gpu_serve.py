@@ -94,3 +94,38 @@ def test_served_least_remaining_work_first(serve):
     for j in jobs:
         o, dg, _ = serve.run_alone(j)
         assert by_seed[j.seed].digest == dg and by_seed[j.seed].obs == o, j
+
+
+def test_served_stream_subset_against_oracle(serve):
+    """The served stream's jobs whose oracle results are stored
+    (tests/golden/c5_subset.json: every job with L <= 256 plus 16 drawn at
+    random, 1008 jobs, up to 10^4 steps each), served together with
+    continuous batching: each final sigma digest, integer counter and v
+    equals the oracle's."""
+    import json
+    import os
+    from paper_2505_05919_amd.workloads import c5_oracle_subset, c5_stream
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_subset.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c5_subset.json not written yet")
+    with open(path) as f:
+        gold = json.load(f)["jobs"]
+    stream = c5_stream()
+    idx = c5_oracle_subset(stream)
+    assert len(idx) == len(gold) == 1008
+    jobs = [stream[n] for n in idx]
+    print(f"case served oracle subset: {len(jobs)} jobs", flush=True)
+    srv = serve.Server(memory_budget=16 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="srpt",
+                       fill_cells=1 << 24)
+    recs = srv.run(jobs, realtime=False)
+    assert len(recs) == len(jobs)
+    by_seed = {r.job.seed: r for r in recs}
+    for n in idx:
+        g = gold[f"j{n:04d}"]["checkpoints"][-1]
+        r = by_seed[stream[n].seed]
+        ctx = (n, stream[n])
+        assert r.digest == g["sha256"], ctx
+        for k in ("n_hb_raw", "n_coop", "count", "met_accepted", "vol_accepted", "step"):
+            assert r.obs[k] == g[k], (ctx, k)
+        assert r.obs["v"] == pytest.approx(g["v"], rel=1e-12), ctx
+        assert r.obs["consistent"] == 1, ctx
