@@ -602,7 +602,7 @@ def main():
         "traffic_gbs": round(traffic / secs / 1e9, 1) if traffic else None,
         "launches_timed": n_launch, "mean_launch_ms": round(mean_ms, 5),
         "algorithmic_bytes_per_launch": alg_bytes, "updates_per_launch": upd_per_launch,
-        "timing": "HIP events around every launch, separate instrumented pass of the same K steps",
+        "timing": "HIP start/stop events recorded by every launch's own dispatch (hipExtLaunchKernel), in a separate instrumented pass of the same K steps",
         "volume_kernel_mean_ms": round(ktimes[cvf.CVF_K_VOLUME][1], 5),
     }
     # The three chains are independent jobs: on three streams of default

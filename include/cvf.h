@@ -220,9 +220,11 @@ int cvf_set_stop(cvf_state *st, int64_t stop_at, void *stream);
 int cvf_tables(const cvf_state *st, uint32_t met[2][3][7], uint64_t sw[3]);
 
 /* Kernel timing.  While enabled, every launch of the kernels of one kind
- * is bracketed by HIP events on the caller's stream.  cvf_kernel_times
- * synchronises those events and returns, for kind k, the number of
- * launches and their mean duration in ms since timing was enabled. */
+ * carries a start/stop pair of HIP events that its own dispatch records
+ * (hipExtLaunchKernel), so each interval is that kernel's execution alone.
+ * cvf_kernel_times synchronises those events and returns, for kind k, the
+ * number of launches and their mean duration in ms since timing was
+ * enabled. */
 #define CVF_K_VOLUME    0   /* volume move / counter fold          */
 #define CVF_K_MET_SWEEP 1   /* one checkerboard colour sweep       */
 #define CVF_K_SW_BONDS  2   /* bond activation + in-tile labels

@@ -127,7 +127,10 @@ int cvf3_state_counts(cvf3_state *st, int64_t *d_counts, void *stream);
 int cvf3_observables(cvf3_state *st, cvf3_obs *out, void *stream);
 
 /* Per-kernel HIP-event timing (off by default): enabling or disabling
- * clears the totals; times are collected when read. */
+ * clears the totals; times are collected when read.  Each launch records
+ * its start/stop events on its own dispatch (the kernel's execution alone);
+ * CVF3_K_SW_UNION and CVF3_K_SW_FLIP span their two and four launches with
+ * events on the stream. */
 #define CVF3_K_VOLUME 0     /* counter fold + volume move + pass order */
 #define CVF3_K_ETA    1     /* eta move over the checkerboard cubes    */
 #define CVF3_K_PASS   2     /* one arm-domain sigma pass               */

@@ -28,6 +28,7 @@
 
 #include "cvf.h"
 #include "cvf3.h"
+#include "dispatch.h"
 
 namespace {
 
@@ -1274,6 +1275,30 @@ int validate3(const cvf_params* p)
     return CVF_OK;
 }
 
+using cvf::DispatchEvents;
+using cvf::go;
+
+// With timing on: start/stop events that the next launch of this kind
+// records on its own dispatch.
+DispatchEvents t_events(cvf3_state* st, int kind)
+{
+    DispatchEvents ev;
+    if (!st->timing) return ev;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return ev;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return ev;
+    }
+    st->ev[kind].push_back(e0);
+    st->ev[kind].push_back(e1);
+    ev.start = e0;
+    ev.stop = e1;
+    return ev;
+}
+
+// Events on the stream around several launches (their interval includes
+// the gaps between them).
 void t_begin(cvf3_state* st, int kind, hipStream_t s)
 {
     if (!st->timing) return;
@@ -1441,28 +1466,33 @@ int cvf3_init(const cvf_params* p, int algo_mask, uint8_t* d_sigma, uint8_t* d_e
     return CVF_OK;
 }
 
+namespace {
+
+// The eta move of one step: two checkerboard cubes per lane when L % 4 == 0.
+hipError_t eta_step(cvf3_state* st, const Lat3& a, hipStream_t s)
+{
+    const DispatchEvents ev = t_events(st, CVF3_K_ETA);
+    if (a.quad) return go(eta3_pair_kernel, dim3(blocks_for(a.N / 8)), dim3(kBlock), s, ev, a);
+    return go(eta3_kernel, dim3(blocks_for(a.N / 4)), dim3(kBlock), s, ev, a);
+}
+
+}  // namespace
+
 int cvf3_steps(cvf3_state* st, int64_t nsteps, void* stream)
 {
     if (!st || nsteps < 0) return CVF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Lat3 a = st->la;
     for (int64_t i = 0; i < nsteps; ++i) {
-        t_begin(st, CVF3_K_VOLUME, s);
-        vol3_kernel<<<1, 64, 0, s>>>(a, kVolMet);
-        t_end(st, CVF3_K_VOLUME, s);
-        t_begin(st, CVF3_K_ETA, s);
-        if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
-        else eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
-        t_end(st, CVF3_K_ETA, s);
+        if (go(vol3_kernel, dim3(1), dim3(64), s, t_events(st, CVF3_K_VOLUME), a, kVolMet) != hipSuccess)
+            return CVF_EHIP;
+        if (eta_step(st, a, s) != hipSuccess) return CVF_EHIP;
+        const unsigned grid = blocks_for(a.quad ? (a.N / 4 + kQuadsPerLane - 1) / kQuadsPerLane : a.N / 2);
         for (uint32_t pass = 0; pass < 6; ++pass) {
             a.pass = pass;
-            t_begin(st, CVF3_K_PASS, s);
-            pass3_kernel<<<blocks_for(a.quad ? (a.N / 4 + kQuadsPerLane - 1) / kQuadsPerLane : a.N / 2), kBlock, 0,
-                           s>>>(a);
-            t_end(st, CVF3_K_PASS, s);
+            if (go(pass3_kernel, dim3(grid), dim3(kBlock), s, t_events(st, CVF3_K_PASS), a) != hipSuccess)
+                return CVF_EHIP;
         }
-        const int rc = hs(hipGetLastError());
-        if (rc != CVF_OK) return rc;
     }
     return CVF_OK;
 }
@@ -1474,16 +1504,12 @@ int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const Lat3& a = st->la;
     for (int64_t i = 0; i < nsteps; ++i) {
-        t_begin(st, CVF3_K_VOLUME, s);
-        vol3_kernel<<<1, 64, 0, s>>>(a, kVolSw);
-        t_end(st, CVF3_K_VOLUME, s);
-        t_begin(st, CVF3_K_ETA, s);
-        if (a.quad) eta3_pair_kernel<<<blocks_for(a.N / 8), kBlock, 0, s>>>(a);
-        else eta3_kernel<<<blocks_for(a.N / 4), kBlock, 0, s>>>(a);
-        t_end(st, CVF3_K_ETA, s);
-        t_begin(st, CVF3_K_SW_BONDS, s);
-        sw3_bonds_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
-        t_end(st, CVF3_K_SW_BONDS, s);
+        if (go(vol3_kernel, dim3(1), dim3(64), s, t_events(st, CVF3_K_VOLUME), a, kVolSw) != hipSuccess)
+            return CVF_EHIP;
+        if (eta_step(st, a, s) != hipSuccess) return CVF_EHIP;
+        if (go(sw3_bonds_kernel, dim3(blocks_for(a.N)), dim3(kBlock), s, t_events(st, CVF3_K_SW_BONDS), a) !=
+            hipSuccess)
+            return CVF_EHIP;
         t_begin(st, CVF3_K_SW_UNION, s);
         // tile phase: 16 x 8 x 8 cells (a sixteenth of the x links and an
         // eighth of the y and z links cross a face) or 8 x 8 x 4

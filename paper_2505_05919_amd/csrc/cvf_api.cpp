@@ -106,24 +106,23 @@ void build_tables(const cvf_params* p, DevTables* t)
 
 int hip_status(hipError_t e) { return e == hipSuccess ? CVF_OK : CVF_EHIP; }
 
-void timing_begin(cvf_state* st, int kind, hipStream_t s)
+// With timing on: a start/stop event pair for the next launch of this kind,
+// which its dispatch records (the kernel's execution time alone).
+DispatchEvents timing_events(cvf_state* st, int kind)
 {
-    if (!st->timing) return;
+    DispatchEvents ev;
+    if (!st->timing) return ev;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return;
+    if (hipEventCreate(&e0) != hipSuccess) return ev;
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
-        return;
+        return ev;
     }
-    (void)hipEventRecord(e0, s);
     st->ev[kind].push_back(e0);
     st->ev[kind].push_back(e1);
-}
-
-void timing_end(cvf_state* st, int kind, hipStream_t s)
-{
-    if (!st->timing || st->ev[kind].empty()) return;
-    (void)hipEventRecord(st->ev[kind].back(), s);
+    ev.start = e0;
+    ev.stop = e1;
+    return ev;
 }
 
 int drain_timing(cvf_state* st)
@@ -144,12 +143,10 @@ int drain_timing(cvf_state* st)
     return rc;
 }
 
-#define TIMED(kind, call)                           \
-    do {                                            \
-        timing_begin(st, kind, s);                  \
-        hipError_t e_ = (call);                     \
-        timing_end(st, kind, s);                    \
-        if (e_ != hipSuccess) return CVF_EHIP;      \
+// A launch whose launcher takes the kind's dispatch events as last argument.
+#define TIMED(kind, launcher, ...)                                                    \
+    do {                                                                              \
+        if ((launcher)(__VA_ARGS__, timing_events(st, kind)) != hipSuccess) return CVF_EHIP; \
     } while (0)
 
 }  // namespace
@@ -313,9 +310,9 @@ int cvf_metropolis_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
     v.mode = kVolMet;
     v.met_att_add = 4 * (int64_t)st->N;
     for (int64_t i = 0; i < nsweeps; ++i) {
-        TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 0, s));
-        TIMED(CVF_K_MET_SWEEP, launch_met_colour(st->la, 1, s));
+        TIMED(CVF_K_VOLUME, launch_volume, v, s);
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour, st->la, 0, s);
+        TIMED(CVF_K_MET_SWEEP, launch_met_colour, st->la, 1, s);
     }
     return CVF_OK;
 }
@@ -328,8 +325,8 @@ int cvf_metropolis_domain_sweeps(cvf_state* st, int64_t nsweeps, void* stream)
     v.mode = kVolMet;
     v.met_att_add = 4 * (int64_t)st->N;
     for (int64_t i = 0; i < nsweeps; ++i) {
-        TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        for (uint32_t pass = 0; pass < 4; ++pass) TIMED(CVF_K_MET_DOMAIN, launch_met_domain(st->la, pass, s));
+        TIMED(CVF_K_VOLUME, launch_volume, v, s);
+        for (uint32_t pass = 0; pass < 4; ++pass) TIMED(CVF_K_MET_DOMAIN, launch_met_domain, st->la, pass, s);
     }
     return CVF_OK;
 }
@@ -343,9 +340,9 @@ int cvf_sw_steps(cvf_state* st, int64_t nsteps, void* stream)
     VolArgs v = st->va;
     v.mode = kVolSw;
     for (int64_t i = 0; i < nsteps; ++i) {
-        TIMED(CVF_K_VOLUME, launch_volume(v, s));
-        TIMED(CVF_K_SW_BONDS, launch_sw_tiles(st->la, s));
-        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles(st->la, s));
+        TIMED(CVF_K_VOLUME, launch_volume, v, s);
+        TIMED(CVF_K_SW_BONDS, launch_sw_tiles, st->la, s);
+        TIMED(CVF_K_SW_FLIP, launch_sw_flip_tiles, st->la, s);
     }
     return CVF_OK;
 }

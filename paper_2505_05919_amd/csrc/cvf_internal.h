@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "cvf.h"
+#include "dispatch.h"
 
 namespace cvf {
 
@@ -158,10 +159,10 @@ hipError_t launch_tables_init(DevTables* dst, const DevTables& src, hipStream_t 
 // (kNoAllocBytes bytes, 256-aligned), looked up once per device.
 hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_volume(const VolArgs& a, hipStream_t s);
-hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s);
+hipError_t launch_volume(const VolArgs& a, hipStream_t s, DispatchEvents ev = {});
+hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s, DispatchEvents ev = {});
 // Arm-domain sweep: pass 0..3 of the step's drawn arm order (any L >= 2).
-hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s);
+hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s, DispatchEvents ev = {});
 // step_gate: the recount closes an SW step and is skipped with it.
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
                           hipStream_t s);
@@ -173,10 +174,10 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
 // Tiled SW step: bonds + in-tile unions + the tile-crossing links (each
 // united by the later of its two tiles), then the cluster shift fused with
 // the recount.  Labels are written out on request.
-hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s, DispatchEvents ev = {});
 // Zero the edge arrival counters (once, when the chain is created).
 hipError_t launch_sw_counters_init(const LatticeArgs& a, hipStream_t s);
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s);
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s, DispatchEvents ev = {});
 hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 // Batched Metropolis: `ent` / `start` are device arrays (count entries,
 // count+1 prefix sums of workgroups); all chains share q; le: every chain's

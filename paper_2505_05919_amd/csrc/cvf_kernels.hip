@@ -326,53 +326,49 @@ hipError_t launch_sigma_init(const LatticeArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_volume(const VolArgs& a, hipStream_t s)
+hipError_t launch_volume(const VolArgs& a, hipStream_t s, DispatchEvents ev)
 {
-    volume_kernel<<<1, 64, 0, s>>>(a);
-    return hipGetLastError();
+    return go(volume_kernel, dim3(1), dim3(64), s, ev, a);
 }
 
 template <int Q, bool R, bool LE>
-void launch_quad_r(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
+hipError_t launch_quad_r(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s, const DispatchEvents& ev)
 {
-    if (colour == 0) met_sweep4_kernel<Q, 0, R, LE><<<grid, 256, 0, s>>>(a);
-    else met_sweep4_kernel<Q, 1, R, LE><<<grid, 256, 0, s>>>(a);
+    if (colour == 0) return go(met_sweep4_kernel<Q, 0, R, LE>, grid, dim3(256), s, ev, a);
+    return go(met_sweep4_kernel<Q, 1, R, LE>, grid, dim3(256), s, ev, a);
 }
 
 template <int Q>
-void launch_quad(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s)
+hipError_t launch_quad(const LatticeArgs& a, int colour, dim3 grid, hipStream_t s, const DispatchEvents& ev)
 {
     if (a.quad == 2) {
-        if (a.met_le) launch_quad_r<Q, true, true>(a, colour, grid, s);
-        else launch_quad_r<Q, true, false>(a, colour, grid, s);
-    } else {
-        if (a.met_le) launch_quad_r<Q, false, true>(a, colour, grid, s);
-        else launch_quad_r<Q, false, false>(a, colour, grid, s);
+        if (a.met_le) return launch_quad_r<Q, true, true>(a, colour, grid, s, ev);
+        return launch_quad_r<Q, true, false>(a, colour, grid, s, ev);
     }
+    if (a.met_le) return launch_quad_r<Q, false, true>(a, colour, grid, s, ev);
+    return launch_quad_r<Q, false, false>(a, colour, grid, s, ev);
 }
 
-hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s)
+hipError_t launch_met_colour(const LatticeArgs& a, int colour, hipStream_t s, DispatchEvents ev)
 {
     if (a.quad) {
         const dim3 grid(((a.L + 3) / 4 + 63) / 64, a.row_blocks);
         switch (a.q) {
-        case 2: launch_quad<2>(a, colour, grid, s); break;
-        case 3: launch_quad<3>(a, colour, grid, s); break;
-        case 4: launch_quad<4>(a, colour, grid, s); break;
-        case 5: launch_quad<5>(a, colour, grid, s); break;
-        default: launch_quad<6>(a, colour, grid, s); break;
+        case 2: return launch_quad<2>(a, colour, grid, s, ev);
+        case 3: return launch_quad<3>(a, colour, grid, s, ev);
+        case 4: return launch_quad<4>(a, colour, grid, s, ev);
+        case 5: return launch_quad<5>(a, colour, grid, s, ev);
+        default: return launch_quad<6>(a, colour, grid, s, ev);
         }
-        return hipGetLastError();
     }
     const dim3 grid((a.L / 2 + 63) / 64, a.row_blocks), block(256);
     switch (a.q) {
-    case 2: met_sweep_kernel<2><<<grid, block, 0, s>>>(a, colour); break;
-    case 3: met_sweep_kernel<3><<<grid, block, 0, s>>>(a, colour); break;
-    case 4: met_sweep_kernel<4><<<grid, block, 0, s>>>(a, colour); break;
-    case 5: met_sweep_kernel<5><<<grid, block, 0, s>>>(a, colour); break;
-    default: met_sweep_kernel<6><<<grid, block, 0, s>>>(a, colour); break;
+    case 2: return go(met_sweep_kernel<2>, grid, block, s, ev, a, colour);
+    case 3: return go(met_sweep_kernel<3>, grid, block, s, ev, a, colour);
+    case 4: return go(met_sweep_kernel<4>, grid, block, s, ev, a, colour);
+    case 5: return go(met_sweep_kernel<5>, grid, block, s, ev, a, colour);
+    default: return go(met_sweep_kernel<6>, grid, block, s, ev, a, colour);
     }
-    return hipGetLastError();
 }
 
 __global__ void set_stop_kernel(DevState* st, int64_t stop_at)
@@ -421,14 +417,15 @@ hipError_t launch_set_stop(DevState* st, int64_t stop_at, hipStream_t s)
 }
 
 template <int Q>
-void launch_domain_q(const LatticeArgs& a, uint32_t pass, dim3 grid, uint32_t rows, hipStream_t s)
+hipError_t launch_domain_q(const LatticeArgs& a, uint32_t pass, dim3 grid, uint32_t rows, hipStream_t s,
+                           const DispatchEvents& ev)
 {
-    if (a.L % 4 == 0) met_domain_kernel<Q, 2><<<grid, 256, 0, s>>>(a, pass, rows);
-    else if (a.L % 2 == 0) met_domain_kernel<Q, 1><<<grid, 256, 0, s>>>(a, pass, rows);
-    else met_domain_kernel<Q, 0><<<grid, 256, 0, s>>>(a, pass, rows);
+    if (a.L % 4 == 0) return go(met_domain_kernel<Q, 2>, grid, dim3(256), s, ev, a, pass, rows);
+    if (a.L % 2 == 0) return go(met_domain_kernel<Q, 1>, grid, dim3(256), s, ev, a, pass, rows);
+    return go(met_domain_kernel<Q, 0>, grid, dim3(256), s, ev, a, pass, rows);
 }
 
-hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s)
+hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s, DispatchEvents ev)
 {
     // lanes own column quads (L % 4 == 0) or pairs, (L + 1) / 2 per row; rows
     // per wavefront for ~8192 wavefronts (measured at L = 4096 with pairs:
@@ -439,13 +436,12 @@ hipError_t launch_met_domain(const LatticeArgs& a, uint32_t pass, hipStream_t s)
     const uint32_t rows = min(32u, (a.L + wpg - 1) / wpg);
     const dim3 grid(groups, ((a.L + rows - 1) / rows + 3) / 4);
     switch (a.q) {
-    case 2: launch_domain_q<2>(a, pass, grid, rows, s); break;
-    case 3: launch_domain_q<3>(a, pass, grid, rows, s); break;
-    case 4: launch_domain_q<4>(a, pass, grid, rows, s); break;
-    case 5: launch_domain_q<5>(a, pass, grid, rows, s); break;
-    default: launch_domain_q<6>(a, pass, grid, rows, s); break;
+    case 2: return launch_domain_q<2>(a, pass, grid, rows, s, ev);
+    case 3: return launch_domain_q<3>(a, pass, grid, rows, s, ev);
+    case 4: return launch_domain_q<4>(a, pass, grid, rows, s, ev);
+    case 5: return launch_domain_q<5>(a, pass, grid, rows, s, ev);
+    default: return launch_domain_q<6>(a, pass, grid, rows, s, ev);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_recount(const LatticeArgs& a, int64_t* out, int spread, int with_counts, int step_gate,
@@ -485,11 +481,10 @@ hipError_t launch_obs_final(DevObs* o, const DevState* st, const DevTables* tab,
     return hipGetLastError();
 }
 
-hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s)
+hipError_t launch_sw_tiles(const LatticeArgs& a, hipStream_t s, DispatchEvents ev)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_tile_kernel<<<grid, kTT, 0, s>>>(a);
-    return hipGetLastError();
+    return go(sw_tile_kernel, grid, dim3(kTT), s, ev, a);
 }
 
 __global__ void sw_counters_init_kernel(uint32_t* ecnt, uint32_t n)
@@ -545,11 +540,10 @@ hipError_t launch_sw_batch(const BatchEntry* ent, const uint32_t* start, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s)
+hipError_t launch_sw_flip_tiles(const LatticeArgs& a, hipStream_t s, DispatchEvents ev)
 {
     const dim3 grid((a.L + kTW - 1) / kTW, (a.L + kTH - 1) / kTH);
-    sw_flip_tile_kernel<<<grid, kTT, 0, s>>>(a);
-    return hipGetLastError();
+    return go(sw_flip_tile_kernel, grid, dim3(kTT), s, ev, a);
 }
 
 hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s)

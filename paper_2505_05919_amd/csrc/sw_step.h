@@ -379,21 +379,7 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
     const uint32_t x = g.x0 + lane;
     const uint32_t vx = col_in ? x : 0u, vxp = col_in ? ((x + 1 == L) ? 0u : x + 1) : 0u;
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(a.sigma, 4 * N), rm = buf_rsrc(a.mask, N);
-    // the bond indices of the thread's cells and their facing arms first:
-    // they do not depend on the chain state, whose loads then overlap them
-    uint32_t sv[kTC / kTT][6];
-#pragma unroll
-    for (uint32_t i = 0; i < kTC / kTT; ++i) {
-        const uint32_t ly = wave + (kTT / 64) * i;
-        const uint32_t y = g.y0 + (ly < g.h ? ly : 0), row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
-        sv[i][0] = ld8(rs, vx, row);
-        sv[i][1] = ld8(rs, vx, N + row);
-        sv[i][2] = ld8(rs, vx, 2 * N + row);
-        sv[i][3] = ld8(rs, vx, 3 * N + row);
-        sv[i][4] = ld8(rs, vxp, N + row);
-        sv[i][5] = ld8(rs, vx, 3 * N + rowp);
-    }
-    if (a.st->skip) return;                    // step limit reached (uniform, before any barrier)
+    if (a.st->skip) return;
     build_incell_lut(lut);
     const SwBondCtx k = sw_ctx(a);
     uint32_t mk[kTC / kTT];
@@ -402,9 +388,11 @@ __device__ __forceinline__ void sw_tile_body(const LatticeArgs& a, const TileGeo
         const uint32_t ly = wave + (kTT / 64) * i;
         uint32_t m = 0;
         if (ly < g.h && col_in) {
-            const uint32_t y = g.y0 + ly, row = y * L;
-            const uint32_t f0 = sv[i][4], f2 = sv[i][5];
-            m = sw_bond_bits(a, k, x + row, sv[i][0], sv[i][1], sv[i][2], sv[i][3], f0, f2);
+            const uint32_t y = g.y0 + ly, row = y * L, rowp = ((y + 1 == L) ? 0u : y + 1) * L;
+            const uint32_t s0 = ld8(rs, vx, row), s1 = ld8(rs, vx, N + row), s2 = ld8(rs, vx, 2 * N + row),
+                           s3 = ld8(rs, vx, 3 * N + row);
+            const uint32_t f0 = ld8(rs, vxp, N + row), f2 = ld8(rs, vx, 3 * N + rowp);
+            m = sw_bond_bits(a, k, x + row, s0, s1, s2, s3, f0, f2);
             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)m, rm, (int)vx, (int)row, 0);
             if (lane == g.w - 1) {
                 edge[ly] = (uint8_t)f0;

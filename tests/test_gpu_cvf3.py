@@ -171,7 +171,7 @@ def run3_mixed(c3, oracle_mod, op, plan):
     return og
 
 
-@pytest.mark.parametrize("L,n", [(2, 10), (4, 6), (6, 4), (8, 3), (16, 2), (18, 2), (36, 1)])
+@pytest.mark.parametrize("L,n", [(2, 10), (4, 6), (6, 4), (8, 3), (16, 2), (18, 2), (24, 2), (32, 2), (36, 1)])
 def test_cvf3_sw_parity(c3, oracle_mod, L, n):
     op = oracle_mod.params_from_si(230.0, 0.1, L=L, seed=900 + L)
     run3_mixed(c3, oracle_mod, op, [("sw", 1), ("sw", n)])
@@ -183,6 +183,15 @@ def test_cvf3_sw_state_points(c3, oracle_mod, T, P, v0):
     (unequal facing arms bond) and a volume crossing v = 2."""
     op = oracle_mod.params_from_si(T, P, L=10, seed=int(T) + 7, v_init=v0, dv_max=0.3 if v0 == 1.9 else 0.0125)
     run3_mixed(c3, oracle_mod, op, [("sw", 2), ("sw", 4)])
+
+
+@pytest.mark.parametrize("L", [16, 24])
+def test_cvf3_sw_tiled_cold(c3, oracle_mod, L):
+    """A cold liquid on tiled lattices (16 x 8 x 8 tiles at L = 16, 8 x 8 x 4
+    at L = 24): clusters span many tiles, so most face links join roots that
+    a neighbouring link of the same face has already joined."""
+    op = oracle_mod.params_from_si(195.0, 0.1, L=L, seed=960 + L, v_init=1.1)
+    run3_mixed(c3, oracle_mod, op, [("sw", 1), ("sw", 3), ("met", 1), ("sw", 1)])
 
 
 @pytest.mark.parametrize("q", [2, 3, 5])
