@@ -655,6 +655,20 @@ def main():
                                     "sigma read and written (8) and a 32-bit label of each of the 4 bond indices "
                                     "written and read (32)",
                            "kernels": swc}}
+        # the three SW jobs on three streams (as for Metropolis above): the
+        # latency-bound tile launches, volume kernels and launch gaps of one
+        # chain overlap another's; aggregate steps/s of the three jobs
+        if not args.skip_concurrent:
+            torch.cuda.synchronize()
+            streams = [torch.cuda.Stream() for _ in sch]
+            for ch, st in zip(sch, streams):
+                ch.stream = st
+            run_blocks(sch, "sw", W * len(sch))
+            t_c = timed(torch, lambda: run_blocks(sch, "sw", KS))
+            sw["concurrent_streams"] = {"streams": len(sch), "steps_per_s": round(KS / t_c, 1),
+                                        "ms_per_step": round(t_c / KS * 1e3, 5)}
+            for ch in sch:
+                ch.stream = None
         log(f"sw: {sw}")
         for ch in sch:
             assert ch.obs()["consistent"] == 1
