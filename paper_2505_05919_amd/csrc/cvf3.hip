@@ -961,7 +961,17 @@ __global__ __launch_bounds__(TX * TY * TZ) void sw3_tile_union_kernel(Lat3 a)
     __shared__ uint32_t lp[6 * T];
     const uint32_t L = a.L, N = a.N;
     const uint32_t tx = L / TX, ty = L / TY;
-    const uint32_t b = blockIdx.x;
+    // Workgroups are dealt to the eight XCDs in turn, and a tile's row of a
+    // plane is TX bytes, a fraction of an L2 line: the j-th workgroup of an
+    // XCD takes tile 8 (8 (j / 8) + xcd) + j % 8, so each XCD works on runs of
+    // 8 tiles along x that share their lines (the last n % 64 tiles keep
+    // their place).
+    const uint32_t nt = gridDim.x;
+    uint32_t b = blockIdx.x;
+    if (b < nt - nt % 64) {
+        const uint32_t xcd = b % 8, j = b / 8;
+        b = ((j / 8) * 8 + xcd) * 8 + j % 8;
+    }
     const uint32_t bx = b % tx, by = (b / tx) % ty, bz = b / (tx * ty);
     const uint32_t t = threadIdx.x, lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
     const uint32_t c = (TX * bx + lx) + L * ((TY * by + ly) + L * (TZ * bz + lz));

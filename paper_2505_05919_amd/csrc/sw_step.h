@@ -213,7 +213,27 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t L, uint32_t bx, uint32_t 
 }
 
 // The tile of this workgroup in a single-chain launch (grid = tiles).
-__device__ __forceinline__ TileGeom grid_tile(uint32_t L) { return tile_geom(L, blockIdx.x, blockIdx.y, gridDim.x); }
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b % 8),
+// each with its own L2, and a tile row of one plane is 64 bytes, half an L2
+// line: with tiles in row-major order every line would be fetched by two
+// XCDs.  Instead the j-th workgroup of an XCD takes tile 32 (8 (j / 32) +
+// xcd) + j % 32, so each XCD works on runs of 32 consecutive tiles and
+// shares lines with other XCDs only at the ends of its runs.  The last
+// n % 256 tiles (the ragged last tile row, which runs after the first
+// round when there are more tiles than workgroup slots) keep their place.
+__device__ __forceinline__ TileGeom grid_tile(uint32_t L)
+{
+    constexpr uint32_t kXcd = 8, kRun = 32;
+    const uint32_t ncx = gridDim.x, n = ncx * gridDim.y;
+    const uint32_t b = blockIdx.x + blockIdx.y * ncx;
+    uint32_t tile = b;
+    if (b < n - n % (kXcd * kRun)) {
+        const uint32_t xcd = b % kXcd, j = b / kXcd;
+        tile = ((j / kRun) * kXcd + xcd) * kRun + j % kRun;
+    }
+    const uint32_t by = tile / ncx;
+    return tile_geom(L, tile - by * ncx, by, ncx);
+}
 
 __device__ __forceinline__ bool tile_in(const TileGeom& g, uint32_t v)
 {
