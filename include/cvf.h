@@ -283,10 +283,11 @@ int cvf_batch_metropolis_sweeps(cvf_batch *b, int64_t nsweeps, int32_t graph_blo
  * every chain has the Swendsen-Wang workspace.  Asynchronous. */
 int cvf_batch_sw_steps(cvf_batch *b, int64_t nsteps, void *stream);
 
-/* Autotuner: times `sweeps` sweeps for each candidate rows value (2, 4, 8,
- * 16, 32) with HIP events and keeps the fastest; *rows_out receives it.
- * The timed sweeps are real: every chain advances by 5 * sweeps steps.
- * Synchronises stream. */
+/* Autotuner: after one untimed block of `sweeps` sweeps, times `sweeps`
+ * sweeps for each candidate rows value (2, 4, 8, 16, 32) with HIP events,
+ * in two rounds, and keeps the candidate with the fastest of its two times;
+ * *rows_out receives it.  The sweeps are real: every chain advances by
+ * 11 * sweeps steps.  Synchronises stream. */
 int cvf_batch_autotune(cvf_batch *b, int32_t sweeps, void *stream, int32_t *rows_out);
 
 /* Release the batch's host state, its captured graph and capture stream;

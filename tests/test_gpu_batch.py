@@ -113,7 +113,7 @@ def test_batch_autotune_and_graph_replays(cvf):
         ch.close()
     for k, (L, T, P, s) in enumerate(jobs):
         ch = cvf.Chain(params(cvf, L, T, P, s), cvf.CVF_ALGO_METROPOLIS)
-        ch.metropolis(5 * 2 + 17)
+        ch.metropolis(11 * 2 + 17)       # the autotuner's 11 blocks of 2 sweeps, then 17
         assert digest(ch) == got[k], k
         ch.close()
 
