@@ -422,8 +422,11 @@ def bench_served(torch, n_jobs, compare_jobs):
     from paper_2505_05919_amd import serve
     from paper_2505_05919_amd.workloads import c5_oracle_subset, c5_stream
     jobs = c5_stream(n_jobs=n_jobs)
+    # sigma digests only for the jobs checked against the oracle (hashing
+    # every served lattice would keep the GPU idle while the host hashes)
+    check = c5_oracle_subset(jobs) if n_jobs == 2000 else []
     srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="srpt",
-                       fill_cells=1 << 24)
+                       fill_cells=1 << 24, digest_seeds=frozenset(jobs[n].seed for n in check))
     recs = srv.run(jobs, realtime=True)
     s = serve.summarize(recs)
     by_seed = {r.job.seed: r for r in recs}

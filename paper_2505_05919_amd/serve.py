@@ -68,6 +68,7 @@ class Server:
     quantum: int = 50                   # MC steps per quantum for every resident job
     graph_block: int = 0                # >0: batched sweeps replay a hipGraph of this many
     keep_digest: bool = False
+    digest_seeds: frozenset | None = None   # with keep_digest: only these jobs' sigma is hashed (None: all)
     policy: AlgoPolicy | None = None    # algorithm choice at arrival (None: as submitted)
     # quantum membership: "all" advances every resident job (processor
     # sharing); "srpt" advances the resident jobs with the least remaining
@@ -174,7 +175,8 @@ class Server:
             for r in running:
                 if r.done >= r.job.nsteps:
                     o = r.chain.obs()
-                    dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if self.keep_digest else ""
+                    hash_it = self.keep_digest and (self.digest_seeds is None or r.job.seed in self.digest_seeds)
+                    dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if hash_it else ""
                     self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
                     used -= footprint(r.job)
                     if r.job.algo == "met":
