@@ -1019,9 +1019,28 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, uint32_t tx_,
             if (y % ty_ != ty_ - 1) m &= ~2u;
             if (z % tz_ != tz_ - 1) m &= ~4u;
         }
+        // A link whose two ends have the same parents as the active link of
+        // the same direction one cell lower along another axis (no wrap) is
+        // already implied: each parent is an ancestor of its end, ancestors
+        // stay ancestors, so equal parents mean the same two components, and
+        // the lower link is united or itself implied by a link lower still.
+        // On a percolating cluster most face links repeat a neighbour's pair.
+        const uint32_t crd[3] = {x, y, z}, stride[3] = {1u, L, L2};
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if ((m >> d) & 1u) uf_unite(a.par, (2 * d) * N + c, (2 * d + 1) * N + nbr[d]);
+        for (int d = 0; d < 3; ++d) {
+            if (!((m >> d) & 1u)) continue;
+            const uint32_t u = (2 * d) * N + c, v = (2 * d + 1) * N + nbr[d];
+            const uint32_t pu = a.par[u], pv = a.par[v];
+            bool implied = false;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                if (e == d || crd[e] == 0) continue;
+                const uint32_t cl = c - stride[e];
+                if (!((a.mask[cl] >> d) & 1u)) continue;
+                if (a.par[(2 * d) * N + cl] == pu && a.par[(2 * d + 1) * N + nbr[d] - stride[e]] == pv) implied = true;
+            }
+            if (!implied) uf_unite(a.par, u, v);
+        }
     }
 }
 
