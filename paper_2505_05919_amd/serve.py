@@ -94,63 +94,110 @@ class Server:
     def run(self, jobs: list[Job], realtime: bool = True) -> list[Record]:
         """Serve `jobs` (sorted by arrival).  realtime: arrivals are released
         by the wall clock from the start of the call; otherwise all jobs are
-        available at once (arrival times are still used for latencies)."""
+        available at once (arrival times are still used for latencies).
+
+        The loop keeps one quantum in flight: it enqueues quantum k + 1 (whose
+        members are known on the host: every job's step count advances at
+        enqueue time) before it waits for quantum k, and retires the jobs that
+        quantum k finished while k + 1 runs.  Host work that touches a chain
+        outside a quantum -- creation, batch descriptor uploads, observables
+        and digests of finished jobs -- goes to a third stream, so that it
+        never waits for the quantum in flight."""
         import hashlib
 
         import torch
         stream_b = torch.cuda.current_stream()
         stream_s = torch.cuda.Stream()             # default priority
+        stream_r = torch.cuda.Stream()             # chain set-up and retirement
         pending = list(jobs)
         queue: list[Job] = []
-        running: list[Running] = []
+        running: list[Running] = []                # admitted, steps left to enqueue
         used = 0
         batch = None
         batch_members: tuple = ()
         swb = None
         swb_members: tuple = ()
+        inflight = None                            # (events, jobs it finishes, batches to close after it)
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0     # noqa: E731
 
-        while pending or queue or running:
+        def retire(q):
+            events, finishing, stale = q
+            tw0 = time.perf_counter()
+            for ev in events:
+                ev.synchronize()
+            tdone = now()
+            tw = time.perf_counter()
+            self.phase_s["wait"] += tw - tw0
+            nonlocal used
+            for b in stale:
+                b.close()
+            with torch.cuda.stream(stream_r):
+                for r in finishing:
+                    r.chain.stream = stream_r      # its quanta are complete; nothing waits for k + 1
+                    o = r.chain.obs()
+                    hash_it = self.keep_digest and (self.digest_seeds is None or r.job.seed in self.digest_seeds)
+                    dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if hash_it else ""
+                    self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
+                    used -= footprint(r.job)
+                    r.chain.close()
+            self.phase_s["retire"] += time.perf_counter() - tw
+
+        while pending or queue or running or inflight is not None:
             tnow = now()
             tp = time.perf_counter()
             while pending and (not realtime or pending[0].arrival <= tnow):
                 job = pending.pop(0)
                 queue.append(self.policy.apply(job) if self.policy else job)
-            # admission: FIFO, by footprint and slots
-            while queue and len(running) < self.max_slots:
+            # admission: FIFO, by footprint and slots (jobs a quantum in flight
+            # finishes still hold their memory until they are retired)
+            held = len(running) + (len(inflight[1]) if inflight is not None else 0)
+            admitted = False
+            while queue and held < self.max_slots:
                 fp = footprint(queue[0])
-                if used + fp > self.memory_budget and running:
+                if used + fp > self.memory_budget and held:
                     break
                 job = queue.pop(0)
                 p = cvf.cvf_params_from_si(job.T, job.P, L=job.L, seed=job.seed)
                 mask = cvf.CVF_ALGO_METROPOLIS | (cvf.CVF_ALGO_SW if job.algo == "sw" else 0)
-                st = stream_s if job.algo == "sw" else stream_b
-                with torch.cuda.stream(st):
-                    ch = cvf.Chain(p, mask, stream=st)
+                with torch.cuda.stream(stream_r):
+                    ch = cvf.Chain(p, mask, stream=stream_r)
                     ch.set_stop(job.nsteps)            # quanta may overshoot; the chain stops exactly
+                ch.stream = stream_s if job.algo == "sw" else stream_b
                 running.append(Running(job, ch, 0, now(), job.arrival if realtime else 0.0))
+                admitted = True
                 used += fp
+                held += 1
                 self.peak_resident_bytes = max(self.peak_resident_bytes, used)
-                self.peak_resident_jobs = max(self.peak_resident_jobs, len(running))
-            if not running:
-                if pending:
-                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.002)))
-                continue
+                self.peak_resident_jobs = max(self.peak_resident_jobs, held)
+            if admitted:
+                stream_r.synchronize()                 # new chains are set up before their first quantum
             tq = time.perf_counter()
             self.phase_s["admit"] += tq - tp
+            if not running:
+                if inflight is not None:
+                    retire(inflight)
+                    inflight = None
+                elif pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.002)))
+                continue
             met = self._members([r for r in running if r.job.algo == "met"])
             sws = self._members([r for r in running if r.job.algo == "sw"])
-            # one quantum: every resident job advances by min(quantum, remaining) steps
+            stale = []
+            events = []
+            # one quantum: every member advances by min(quantum, remaining) steps
             if met:
                 steps = min(self.quantum, max(r.job.nsteps - r.done for r in met))
                 members = tuple(id(r) for r in met)
                 if members != batch_members:
                     if batch is not None:
-                        batch.close()
-                    batch = cvf.Batch([r.chain for r in met], stream=stream_b)
+                        stale.append(batch)            # closed once the quantum in flight is done
+                    batch = cvf.Batch([r.chain for r in met], stream=stream_r)
+                    batch.stream = stream_b
                     batch_members = members
                 batch.metropolis(steps, graph_block=self.graph_block if steps % max(1, self.graph_block) == 0 else 0)
+                events.append(torch.cuda.Event())
+                events[-1].record(stream_b)
                 for r in met:
                     r.done = min(r.done + steps, r.job.nsteps)
             if sws:
@@ -158,46 +205,31 @@ class Server:
                 members = tuple(id(r) for r in sws)
                 if members != swb_members:
                     if swb is not None:
-                        swb.close()
-                    swb = cvf.Batch([r.chain for r in sws], stream=stream_s)
+                        stale.append(swb)
+                    swb = cvf.Batch([r.chain for r in sws], stream=stream_r)
+                    swb.stream = stream_s
                     swb_members = members
                 swb.sw(n)
+                events.append(torch.cuda.Event())
+                events[-1].record(stream_s)
                 for r in sws:
                     r.done = min(r.done + n, r.job.nsteps)
-            tl = time.perf_counter()
-            self.phase_s["launch"] += tl - tq
-            torch.cuda.synchronize()
+            finishing = [r for r in running if r.done >= r.job.nsteps]
+            running = [r for r in running if r.done < r.job.nsteps]
+            if finishing:
+                # a finished job leaves its batch: rebuild at the next quantum
+                if any(r.job.algo == "met" for r in finishing):
+                    batch_members = ()
+                if any(r.job.algo == "sw" for r in finishing):
+                    swb_members = ()
             self.quanta += 1
-            tdone = now()
-            tw = time.perf_counter()
-            self.phase_s["wait"] += tw - tl
-            still = []
-            for r in running:
-                if r.done >= r.job.nsteps:
-                    o = r.chain.obs()
-                    hash_it = self.keep_digest and (self.digest_seeds is None or r.job.seed in self.digest_seeds)
-                    dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if hash_it else ""
-                    self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
-                    used -= footprint(r.job)
-                    if r.job.algo == "met":
-                        batch_members = ()          # membership changes
-                    else:
-                        swb_members = ()
-                    r.chain.close()
-                else:
-                    still.append(r)
-            if batch is not None and batch_members == ():
-                batch.close()
-                batch = None
-            if swb is not None and swb_members == ():
-                swb.close()
-                swb = None
-            running = still
-            self.phase_s["retire"] += time.perf_counter() - tw
-        if batch is not None:
-            batch.close()
-        if swb is not None:
-            swb.close()
+            self.phase_s["launch"] += time.perf_counter() - tq
+            if inflight is not None:
+                retire(inflight)
+            inflight = (events, finishing, stale)
+        for b in (batch, swb):
+            if b is not None:
+                b.close()
         return self.records
 
 
