@@ -791,11 +791,22 @@ __device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t 
     return lo;
 }
 
-__device__ __forceinline__ TileGeom batch_tile(const LatticeArgs& a, uint32_t local)
+// Tile of workgroup b of a batch whose chain's tiles are start .. end - 1:
+// the XCD-aware order of grid_tile over the workgroups from the first
+// multiple of 256 at or after start, in whole groups of 256 (so that
+// b % 8 is the XCD there too); row-major order elsewhere.
+__device__ __forceinline__ TileGeom batch_tile(const LatticeArgs& a, uint32_t b, uint32_t start, uint32_t end)
 {
+    constexpr uint32_t kXcd = 8, kRun = 32, kGroup = kXcd * kRun;
     const uint32_t ncx = (a.L + kTW - 1) / kTW;
-    const uint32_t by = local / ncx;
-    return tile_geom(a.L, local - by * ncx, by, ncx);
+    const uint32_t s8 = (start + kGroup - 1) / kGroup * kGroup;
+    uint32_t tile = b - start;
+    if (b >= s8 && end >= s8 && b < s8 + (end - s8) / kGroup * kGroup) {
+        const uint32_t r = b - s8, xcd = r % kXcd, j = r / kXcd;
+        tile = s8 - start + ((j / kRun) * kXcd + xcd) * kRun + j % kRun;
+    }
+    const uint32_t by = tile / ncx;
+    return tile_geom(a.L, tile - by * ncx, by, ncx);
 }
 
 __global__ __launch_bounds__(kTT) void sw_tile_batch_kernel(const BatchEntry* __restrict__ ent,
@@ -806,7 +817,7 @@ __global__ __launch_bounds__(kTT) void sw_tile_batch_kernel(const BatchEntry* __
     __shared__ uint8_t act[kEdgeBytes];
     const uint32_t c = batch_chain(tstart, count, blockIdx.x);
     const LatticeArgs a = ent[c].la;
-    sw_tile_body(a, batch_tile(a, blockIdx.x - tstart[c]), lut, lab, act);
+    sw_tile_body(a, batch_tile(a, blockIdx.x, tstart[c], tstart[c + 1]), lut, lab, act);
 }
 
 __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) void sw_flip_batch_kernel(
@@ -815,5 +826,5 @@ __global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     __shared__ FlipLds lds;
     const uint32_t c = batch_chain(tstart, count, blockIdx.x);
     const LatticeArgs a = ent[c].la;
-    sw_flip_body(a, batch_tile(a, blockIdx.x - tstart[c]), lds);
+    sw_flip_body(a, batch_tile(a, blockIdx.x, tstart[c], tstart[c + 1]), lds);
 }
