@@ -36,7 +36,9 @@
  *  - stream: a hipStream_t passed as void* (NULL = the null stream).  All
  *    calls are asynchronous on that stream except cvf_observables,
  *    cvf_labels, cvf_kernel_times, cvf_batch_create, cvf_batch_set_rows and
- *    cvf_batch_autotune, which synchronise it.
+ *    cvf_batch_autotune, which synchronise it.  cvf_init writes its tables
+ *    with a kernel (no host copy), so it never waits for earlier work on
+ *    its stream.
  *  - Threading: a cvf_state is not thread-safe; distinct states are
  *    independent and may run concurrently on different streams.
  */
@@ -183,6 +185,14 @@ int cvf_sw_steps_noalloc(const cvf_params *p, uint8_t *d_sigma, int64_t nsteps, 
  * *out.  Synchronises stream. */
 int cvf_observables(cvf_state *st, cvf_obs *out, void *stream);
 
+/* The same record (Eq. (1), (3), the counts of Sec. III.A) without
+ * synchronising: it is written to out -- device memory, or pinned host
+ * memory such as hipHostMalloc gives, 8-byte aligned -- when the stream
+ * reaches this call's work, so that a caller (a server retiring finished
+ * jobs while later ones run) never waits for earlier work on the stream.
+ * CVF_EINVAL for a NULL state or a NULL or misaligned out. */
+int cvf_observables_async(cvf_state *st, cvf_obs *out, void *stream);
+
 /* Add the state counts N_q' of the current configuration (the number of
  * bond indices in state q', q' = 0..5, from which Sec. III.A builds the
  * order parameter M = max N_q' over the number of bond indices, 4N in 2-D,
@@ -263,6 +273,15 @@ int cvf_batch_desc_bytes(int32_t count, size_t *bytes);
  * and waits for the copy. */
 int cvf_batch_create(cvf_state *const *chains, int32_t count, void *d_desc, size_t desc_bytes,
                      void *stream, cvf_batch **out);
+
+/* As cvf_batch_create, without waiting for the upload: the descriptor table
+ * is written into h_staging -- caller-owned pinned host memory (such as
+ * hipHostMalloc gives) of staging_bytes >= desc_bytes -- and copied on
+ * stream; h_staging must stay unchanged until the stream has passed this
+ * call.  For callers that rebuild batches while earlier work runs on the
+ * stream.  CVF_EINVAL also for a NULL or small staging buffer. */
+int cvf_batch_create_async(cvf_state *const *chains, int32_t count, void *d_desc, size_t desc_bytes,
+                           void *h_staging, size_t staging_bytes, void *stream, cvf_batch **out);
 
 /* Launch shape of the batched Metropolis pass: a chain's colour pass is cut
  * into work units of two rows times a column quad (L % 4 == 0) or a column

@@ -294,7 +294,7 @@ int cvf_init(const cvf_params* p, uint8_t* d_sigma, void* d_work, size_t work_by
     cvf_state* st = new (std::nothrow) cvf_state();
     if (!st) return CVF_EINVAL;
     chain_setup(p, d_sigma, (char*)d_work, work_bytes, st);
-    if (chain_start(st, false, (hipStream_t)stream) != hipSuccess) {
+    if (chain_start(st, true, (hipStream_t)stream) != hipSuccess) {
         delete st;
         return CVF_EHIP;
     }
@@ -369,10 +369,11 @@ int cvf_sw_steps_noalloc(const cvf_params* p, uint8_t* d_sigma, int64_t nsteps, 
     return cvf_observables(&st, out, stream);
 }
 
-int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
+namespace {
+
+// The recount and the observables record in the workspace (DevObs::out).
+hipError_t observables_launch(cvf_state* st, hipStream_t s)
 {
-    if (!st || !out) return CVF_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
     VolArgs v = st->va;
     v.mode = kVolFold;
     hipError_t e = launch_volume(v, s);
@@ -381,6 +382,25 @@ int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
     if (e == hipSuccess)
         e = launch_obs_final(st->dobs, st->dst, st->dtab, (double)st->N, st->p.J, st->p.Jsigma, st->p.P,
                              st->p.vHB, s);
+    return e;
+}
+
+}  // namespace
+
+int cvf_observables_async(cvf_state* st, cvf_obs* out, void* stream)
+{
+    if (!st || !out || ((uintptr_t)out & 7) != 0) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = observables_launch(st, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, &st->dobs->out, sizeof(cvf_obs), hipMemcpyDefault, s);
+    return hip_status(e);
+}
+
+int cvf_observables(cvf_state* st, cvf_obs* out, void* stream)
+{
+    if (!st || !out) return CVF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = observables_launch(st, s);
     cvf_obs tmp;
     if (e == hipSuccess) e = hipMemcpyAsync(&tmp, &st->dobs->out, sizeof(cvf_obs), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -469,7 +489,7 @@ struct cvf_batch {
     int q;
     int le;                           // every chain's table allows the one-compare acceptance
     int32_t rows;                     // 0 = per-chain default
-    hipStream_t capture;              // private stream for graph capture
+    hipStream_t capture;              // private stream for graph capture (created at the first capture)
     hipGraphExec_t exec;
     int32_t exec_block;               // sweeps held by exec (0 = none)
 };
@@ -495,7 +515,7 @@ void drop_graph(cvf_batch* b)
     b->exec_block = 0;
 }
 
-int batch_upload(cvf_batch* b, hipStream_t s)
+int batch_upload(cvf_batch* b, hipStream_t s, uint8_t* staging)
 {
     const uint32_t count = (uint32_t)b->chains.size();
     b->host.resize(count);
@@ -533,6 +553,17 @@ int batch_upload(cvf_batch* b, hipStream_t s)
     b->tstart[count] = ttotal;
     b->total_blocks = total;
     b->sw_tiles = ttotal;
+    if (staging) {
+        // the descriptor image, laid out as on the device, in the caller's
+        // pinned staging: one copy, nothing to wait for
+        const size_t off_start = (size_t)((char*)b->d_start - (char*)b->d_ent);
+        const size_t off_tstart = (size_t)((char*)b->d_tstart - (char*)b->d_ent);
+        memcpy(staging, b->host.data(), count * sizeof(BatchEntry));
+        memcpy(staging + off_start, b->start.data(), (count + 1) * sizeof(uint32_t));
+        memcpy(staging + off_tstart, b->tstart.data(), (count + 1) * sizeof(uint32_t));
+        return hip_status(hipMemcpyAsync(b->d_ent, staging, off_tstart + (count + 1) * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, s));
+    }
     hipError_t e = hipMemcpyAsync(b->d_ent, b->host.data(), count * sizeof(BatchEntry), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_start, b->start.data(), (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
@@ -555,6 +586,7 @@ hipError_t batch_sweep(cvf_batch* b, hipStream_t s)
 int batch_capture(cvf_batch* b, int32_t block)
 {
     drop_graph(b);
+    if (!b->capture && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) return CVF_EHIP;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
     for (int32_t i = 0; e == hipSuccess && i < block; ++i) e = batch_sweep(b, b->capture);
@@ -580,9 +612,15 @@ int cvf_batch_desc_bytes(int32_t count, size_t* bytes)
     return CVF_OK;
 }
 
-int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size_t desc_bytes, void* stream,
-                     cvf_batch** out)
+namespace {
+
+// Both creation calls: h_staging NULL uploads from the batch's host vectors
+// and waits; otherwise the table is written into the caller's pinned
+// staging (staging_bytes >= desc_bytes) and copied without waiting.
+int batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size_t desc_bytes, void* h_staging,
+                 size_t staging_bytes, void* stream, cvf_batch** out)
 {
+    (void)staging_bytes;
     if (!chains || count <= 0 || !d_desc || !out) return CVF_EINVAL;
     if (((uintptr_t)d_desc & 255) != 0) return CVF_EINVAL;
     size_t off_start, off_tstart;
@@ -604,13 +642,9 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
     b->rows = 0;
     b->exec = nullptr;
     b->exec_block = 0;
-    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
-        delete b;
-        return CVF_EHIP;
-    }
-    int rc = batch_upload(b, (hipStream_t)stream);
+    b->capture = nullptr;
+    int rc = batch_upload(b, (hipStream_t)stream, (uint8_t*)h_staging);
     if (rc) {
-        (void)hipStreamDestroy(b->capture);
         delete b;
         return rc;
     }
@@ -618,12 +652,27 @@ int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size
     return CVF_OK;
 }
 
+}  // namespace
+
+int cvf_batch_create(cvf_state* const* chains, int32_t count, void* d_desc, size_t desc_bytes, void* stream,
+                     cvf_batch** out)
+{
+    return batch_create(chains, count, d_desc, desc_bytes, nullptr, 0, stream, out);
+}
+
+int cvf_batch_create_async(cvf_state* const* chains, int32_t count, void* d_desc, size_t desc_bytes,
+                           void* h_staging, size_t staging_bytes, void* stream, cvf_batch** out)
+{
+    if (!h_staging || staging_bytes < desc_bytes) return CVF_EINVAL;
+    return batch_create(chains, count, d_desc, desc_bytes, h_staging, staging_bytes, stream, out);
+}
+
 int cvf_batch_set_rows(cvf_batch* b, int32_t rows, void* stream)
 {
     if (!b || rows < 0 || rows > 32 || (rows & 1)) return CVF_EINVAL;
     drop_graph(b);
     b->rows = rows;
-    return batch_upload(b, (hipStream_t)stream);
+    return batch_upload(b, (hipStream_t)stream, nullptr);
 }
 
 int cvf_batch_metropolis_sweeps(cvf_batch* b, int64_t nsweeps, int32_t graph_block, void* stream)
@@ -710,7 +759,7 @@ int cvf_batch_destroy(cvf_batch* b)
 {
     if (!b) return CVF_EINVAL;
     drop_graph(b);
-    (void)hipStreamDestroy(b->capture);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
     delete b;
     return CVF_OK;
 }

@@ -25,7 +25,7 @@ EXPORTS = ["cvf_params_from_si", "cvf_workspace_bytes", "cvf_init", "cvf_metropo
            "cvf_sw_steps", "cvf_observables", "cvf_labels", "cvf_tables", "cvf_timing_enable",
            "cvf_kernel_times", "cvf_destroy", "cvf_strerror", "cvf_set_stop", "cvf_batch_desc_bytes", "cvf_batch_create",
            "cvf_batch_set_rows", "cvf_batch_metropolis_sweeps", "cvf_batch_sw_steps", "cvf_batch_autotune",
-           "cvf_batch_destroy", "cvf_sw_steps_noalloc"]
+           "cvf_batch_destroy", "cvf_sw_steps_noalloc", "cvf_observables_async", "cvf_batch_create_async"]
 
 
 class CvfError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
         L.cvf_state_counts.argtypes = [vp, vp, vp]
         L.cvf_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_observables.argtypes = [vp, ctypes.POINTER(cvf_obs), vp]
+        L.cvf_observables_async.argtypes = [vp, vp, vp]
         L.cvf_labels.argtypes = [vp, vp, vp]
         L.cvf_set_stop.argtypes = [vp, ctypes.c_int64, vp]
         L.cvf_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)]
@@ -87,6 +88,8 @@ def lib():
         L.cvf_batch_desc_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.cvf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.c_size_t, vp,
                                        ctypes.POINTER(vp)]
+        L.cvf_batch_create_async.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.c_size_t, vp,
+                                             ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.cvf_batch_set_rows.argtypes = [vp, ctypes.c_int32, vp]
         L.cvf_batch_metropolis_sweeps.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp]
         L.cvf_batch_sw_steps.argtypes = [vp, ctypes.c_int64, vp]
@@ -189,6 +192,13 @@ def cvf_observables(st, stream=None) -> dict:
     return o.as_dict()
 
 
+def cvf_observables_async(st, out_ptr: int, stream=None):
+    """Enqueue the observables record into out_ptr (device or pinned host
+    memory, 8-byte aligned; read it as cvf_obs.from_address once the stream
+    has passed this call)."""
+    _check("cvf_observables_async", lib().cvf_observables_async(st, ctypes.c_void_p(out_ptr), _stream(stream)))
+
+
 def cvf_labels(st, out, stream=None):
     op, _ = _devptr(out, "torch.int32", 4)
     _check("cvf_labels", lib().cvf_labels(st, op, _stream(stream)))
@@ -236,6 +246,22 @@ def cvf_batch_create(handles, desc, stream=None) -> ctypes.c_void_p:
     return b
 
 
+def cvf_batch_create_async(handles, desc, staging, stream=None) -> ctypes.c_void_p:
+    """cvf_batch_create without waiting: staging is a pinned host uint8 tensor
+    of at least desc.numel() bytes, kept unchanged until the stream has passed
+    the upload."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    dp, nbytes = _devptr(desc, "torch.uint8", 1)
+    if not staging.is_pinned() or staging.numel() < nbytes:
+        raise CvfError("cvf_batch_create_async", CVF_EINVAL)
+    b = ctypes.c_void_p()
+    _check("cvf_batch_create_async", lib().cvf_batch_create_async(arr, len(handles), dp, nbytes,
+                                                                  ctypes.c_void_p(staging.data_ptr()),
+                                                                  staging.numel(), _stream(stream),
+                                                                  ctypes.byref(b)))
+    return b
+
+
 def cvf_batch_set_rows(b, rows: int, stream=None):
     _check("cvf_batch_set_rows", lib().cvf_batch_set_rows(b, rows, _stream(stream)))
 
@@ -262,12 +288,19 @@ class Batch:
     """Owner of a batch's descriptor buffer; the chains stay owned by their
     Chain objects (which must outlive the batch)."""
 
-    def __init__(self, chains, stream=None):
+    def __init__(self, chains, stream=None, nowait=False):
+        """nowait: upload the descriptor table from a pinned staging buffer
+        (kept with the batch) without waiting for earlier work on stream."""
         import torch
         self.chains = list(chains)
-        self.desc = torch.empty(cvf_batch_desc_bytes(len(self.chains)), dtype=torch.uint8, device="cuda")
+        nbytes = cvf_batch_desc_bytes(len(self.chains))
+        self.desc = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream
-        self.h = cvf_batch_create([c.h for c in self.chains], self.desc, stream)
+        if nowait:
+            self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+            self.h = cvf_batch_create_async([c.h for c in self.chains], self.desc, self.staging, stream)
+        else:
+            self.h = cvf_batch_create([c.h for c in self.chains], self.desc, stream)
 
     def metropolis(self, n, graph_block=0):
         cvf_batch_metropolis_sweeps(self.h, n, graph_block, self.stream)

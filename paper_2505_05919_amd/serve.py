@@ -82,9 +82,10 @@ class Server:
     peak_resident_jobs: int = 0
     quanta: int = 0
     # wall seconds per part of the loop: admission (chain creation), enqueueing
-    # the quantum's launches (and batch rebuilds), waiting for the GPU, retiring
-    # finished jobs (observables, digests)
-    phase_s: dict = field(default_factory=lambda: {"admit": 0.0, "launch": 0.0, "wait": 0.0, "retire": 0.0})
+    # the quantum's launches (of which batch rebuilds), waiting for the GPU,
+    # retiring finished jobs (of which sigma digests)
+    phase_s: dict = field(default_factory=lambda: {"admit": 0.0, "launch": 0.0, "wait": 0.0, "retire": 0.0,
+                                                   "rebuild": 0.0, "digest": 0.0})
 
     def _members(self, runs: list) -> list:
         if self.schedule == "srpt":
@@ -96,19 +97,21 @@ class Server:
         by the wall clock from the start of the call; otherwise all jobs are
         available at once (arrival times are still used for latencies).
 
-        The loop keeps one quantum in flight: it enqueues quantum k + 1 (whose
-        members are known on the host: every job's step count advances at
-        enqueue time) before it waits for quantum k, and retires the jobs that
-        quantum k finished while k + 1 runs.  Host work that touches a chain
-        outside a quantum -- creation, batch descriptor uploads, observables
-        and digests of finished jobs -- goes to a third stream, so that it
-        never waits for the quantum in flight."""
+        The loop keeps one quantum in flight: every job's step count advances
+        when its quantum is enqueued, so the members of quantum k + 1 are
+        known before quantum k ends; the loop enqueues k + 1 (behind k on the
+        same streams) and only then waits for k.  Nothing the host does
+        between quanta waits for the GPU: chains are created with kernels
+        only, batches upload their descriptors from pinned staging, and a
+        finishing job's observables (and sigma, when digested) are copied to
+        pinned host memory on its stream right after its last quantum, to be
+        read once that quantum's event has completed."""
+        import ctypes
         import hashlib
 
         import torch
         stream_b = torch.cuda.current_stream()
         stream_s = torch.cuda.Stream()             # default priority
-        stream_r = torch.cuda.Stream()             # chain set-up and retirement
         pending = list(jobs)
         queue: list[Job] = []
         running: list[Running] = []                # admitted, steps left to enqueue
@@ -117,9 +120,25 @@ class Server:
         batch_members: tuple = ()
         swb = None
         swb_members: tuple = ()
-        inflight = None                            # (events, jobs it finishes, batches to close after it)
+        inflight = None                            # (events, [(run, obs buffer, sigma copy)], batches to close)
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0     # noqa: E731
+        obs_bytes = ctypes.sizeof(cvf.cvf_obs)
+
+        def collect(runs, st):
+            """Enqueue on st, behind the runs' last quantum, the copies their
+            retirement reads."""
+            out = []
+            with torch.cuda.stream(st):
+                for r in runs:
+                    ob = torch.empty(obs_bytes, dtype=torch.uint8, pin_memory=True)
+                    cvf.cvf_observables_async(r.chain.h, ob.data_ptr(), st)
+                    sg = None
+                    if self.keep_digest and (self.digest_seeds is None or r.job.seed in self.digest_seeds):
+                        sg = torch.empty(r.chain.sigma.numel(), dtype=torch.uint8, pin_memory=True)
+                        sg.copy_(r.chain.sigma, non_blocking=True)
+                    out.append((r, ob, sg))
+            return out
 
         def retire(q):
             events, finishing, stale = q
@@ -132,15 +151,14 @@ class Server:
             nonlocal used
             for b in stale:
                 b.close()
-            with torch.cuda.stream(stream_r):
-                for r in finishing:
-                    r.chain.stream = stream_r      # its quanta are complete; nothing waits for k + 1
-                    o = r.chain.obs()
-                    hash_it = self.keep_digest and (self.digest_seeds is None or r.job.seed in self.digest_seeds)
-                    dg = hashlib.sha256(r.chain.sigma.cpu().numpy().tobytes()).hexdigest() if hash_it else ""
-                    self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
-                    used -= footprint(r.job)
-                    r.chain.close()
+            for r, ob, sg in finishing:
+                o = cvf.cvf_obs.from_buffer_copy(ob.numpy().tobytes()).as_dict()
+                tb = time.perf_counter()
+                dg = hashlib.sha256(sg.numpy().tobytes()).hexdigest() if sg is not None else ""
+                self.phase_s["digest"] += time.perf_counter() - tb
+                self.records.append(Record(r.job, r.admitted_at, tdone, o, dg, r.t_ref))
+                used -= footprint(r.job)
+                r.chain.close()
             self.phase_s["retire"] += time.perf_counter() - tw
 
         while pending or queue or running or inflight is not None:
@@ -152,7 +170,6 @@ class Server:
             # admission: FIFO, by footprint and slots (jobs a quantum in flight
             # finishes still hold their memory until they are retired)
             held = len(running) + (len(inflight[1]) if inflight is not None else 0)
-            admitted = False
             while queue and held < self.max_slots:
                 fp = footprint(queue[0])
                 if used + fp > self.memory_budget and held:
@@ -160,18 +177,15 @@ class Server:
                 job = queue.pop(0)
                 p = cvf.cvf_params_from_si(job.T, job.P, L=job.L, seed=job.seed)
                 mask = cvf.CVF_ALGO_METROPOLIS | (cvf.CVF_ALGO_SW if job.algo == "sw" else 0)
-                with torch.cuda.stream(stream_r):
-                    ch = cvf.Chain(p, mask, stream=stream_r)
+                st = stream_s if job.algo == "sw" else stream_b
+                with torch.cuda.stream(st):
+                    ch = cvf.Chain(p, mask, stream=st)
                     ch.set_stop(job.nsteps)            # quanta may overshoot; the chain stops exactly
-                ch.stream = stream_s if job.algo == "sw" else stream_b
                 running.append(Running(job, ch, 0, now(), job.arrival if realtime else 0.0))
-                admitted = True
                 used += fp
                 held += 1
                 self.peak_resident_bytes = max(self.peak_resident_bytes, used)
                 self.peak_resident_jobs = max(self.peak_resident_jobs, held)
-            if admitted:
-                stream_r.synchronize()                 # new chains are set up before their first quantum
             tq = time.perf_counter()
             self.phase_s["admit"] += tq - tp
             if not running:
@@ -183,8 +197,7 @@ class Server:
                 continue
             met = self._members([r for r in running if r.job.algo == "met"])
             sws = self._members([r for r in running if r.job.algo == "sw"])
-            stale = []
-            events = []
+            stale, events, finishing = [], [], []
             # one quantum: every member advances by min(quantum, remaining) steps
             if met:
                 steps = min(self.quantum, max(r.job.nsteps - r.done for r in met))
@@ -192,35 +205,38 @@ class Server:
                 if members != batch_members:
                     if batch is not None:
                         stale.append(batch)            # closed once the quantum in flight is done
-                    batch = cvf.Batch([r.chain for r in met], stream=stream_r)
-                    batch.stream = stream_b
+                    tr = time.perf_counter()
+                    batch = cvf.Batch([r.chain for r in met], stream=stream_b, nowait=True)
+                    self.phase_s["rebuild"] += time.perf_counter() - tr
                     batch_members = members
                 batch.metropolis(steps, graph_block=self.graph_block if steps % max(1, self.graph_block) == 0 else 0)
-                events.append(torch.cuda.Event())
-                events[-1].record(stream_b)
                 for r in met:
                     r.done = min(r.done + steps, r.job.nsteps)
+                finishing += collect([r for r in met if r.done >= r.job.nsteps], stream_b)
+                events.append(torch.cuda.Event())
+                events[-1].record(stream_b)
             if sws:
                 n = min(self.quantum, max(r.job.nsteps - r.done for r in sws))
                 members = tuple(id(r) for r in sws)
                 if members != swb_members:
                     if swb is not None:
                         stale.append(swb)
-                    swb = cvf.Batch([r.chain for r in sws], stream=stream_r)
-                    swb.stream = stream_s
+                    tr = time.perf_counter()
+                    swb = cvf.Batch([r.chain for r in sws], stream=stream_s, nowait=True)
+                    self.phase_s["rebuild"] += time.perf_counter() - tr
                     swb_members = members
                 swb.sw(n)
-                events.append(torch.cuda.Event())
-                events[-1].record(stream_s)
                 for r in sws:
                     r.done = min(r.done + n, r.job.nsteps)
-            finishing = [r for r in running if r.done >= r.job.nsteps]
+                finishing += collect([r for r in sws if r.done >= r.job.nsteps], stream_s)
+                events.append(torch.cuda.Event())
+                events[-1].record(stream_s)
             running = [r for r in running if r.done < r.job.nsteps]
             if finishing:
                 # a finished job leaves its batch: rebuild at the next quantum
-                if any(r.job.algo == "met" for r in finishing):
+                if any(r.job.algo == "met" for r, _, _ in finishing):
                     batch_members = ()
-                if any(r.job.algo == "sw" for r in finishing):
+                if any(r.job.algo == "sw" for r, _, _ in finishing):
                     swb_members = ()
             self.quanta += 1
             self.phase_s["launch"] += time.perf_counter() - tq

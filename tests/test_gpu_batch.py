@@ -206,3 +206,45 @@ def test_step_limit(cvf):
     b.close()
     for ch in chains:
         ch.close()
+
+
+def test_batch_create_async_and_observables_async(cvf):
+    """The no-wait variants give the same results: a batch created from pinned
+    staging (behind earlier work on its stream) sweeps exactly as one created
+    with the waiting upload, and the observables record copied to pinned host
+    memory without synchronising equals cvf_observables."""
+    import ctypes
+    import torch
+    jobs = mixed_jobs(12, seed=21)
+    s = torch.cuda.Stream()
+    a = [cvf.Chain(params(cvf, L, T, P, sd), cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW, stream=s)
+         for L, T, P, sd in jobs]
+    b = [cvf.Chain(params(cvf, L, T, P, sd), cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW) for L, T, P, sd in jobs]
+    ba = cvf.Batch(a, stream=s, nowait=True)
+    bb = cvf.Batch(b)
+    ba.metropolis(7)
+    bb.metropolis(7)
+    ba.sw(3)
+    bb.sw(3)
+    ba2 = cvf.Batch(a[::2], stream=s, nowait=True)       # rebuilt while the sweeps may still run
+    ba2.metropolis(4)
+    bb2 = cvf.Batch(b[::2])
+    bb2.metropolis(4)
+    n = ctypes.sizeof(cvf.cvf_obs)
+    bufs = []
+    for ch in a:
+        buf = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        cvf.cvf_observables_async(ch.h, buf.data_ptr(), s)
+        bufs.append(buf)
+    s.synchronize()
+    torch.cuda.synchronize()
+    for k, (ca, cb) in enumerate(zip(a, b)):
+        assert digest(ca) == digest(cb), k
+        got = cvf.cvf_obs.from_buffer_copy(bufs[k].numpy().tobytes()).as_dict()
+        assert got == cb.obs(), k
+    with pytest.raises(cvf.CvfError):
+        cvf.cvf_observables_async(a[0].h, bufs[0].data_ptr() + 4, s)   # misaligned
+    for x in (ba, bb, ba2, bb2):
+        x.close()
+    for ch in a + b:
+        ch.close()
