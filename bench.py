@@ -425,7 +425,7 @@ def bench_served(torch, n_jobs, compare_jobs):
     # sigma digests only for the jobs checked against the oracle (hashing
     # every served lattice would keep the GPU idle while the host hashes)
     check = c5_oracle_subset(jobs) if n_jobs == 2000 else []
-    srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="srpt",
+    srv = serve.Server(memory_budget=32 << 30, max_slots=1024, quantum=100, keep_digest=True, schedule="srpt",
                        fill_cells=1 << 24, digest_seeds=frozenset(jobs[n].seed for n in check))
     recs = srv.run(jobs, realtime=True)
     s = serve.summarize(recs)
@@ -452,7 +452,7 @@ def bench_served(torch, n_jobs, compare_jobs):
     met_upd = sum(4 * j.L ** 2 * j.nsteps for j in jobs if j.algo == "met")
     sw_cells = sum(j.L ** 2 * j.nsteps for j in jobs if j.algo == "sw")
     span_arr = max(j.arrival for j in jobs)
-    out = {"jobs": n_jobs, "rate_per_s": 200.0, "quantum": srv.quantum,
+    out = {"jobs": n_jobs, "rate_per_s": 200.0, "quantum": srv.quantum, "max_resident_jobs": srv.max_slots,
            "schedule": "least remaining work first, >= 2^24 cells per quantum",
            "p50_ms": round(s["p50_s"] * 1e3, 1), "p99_ms": round(s["p99_s"] * 1e3, 1),
            "queue_p50_ms": round(s["queue_p50_s"] * 1e3, 1), "queue_p99_ms": round(s["queue_p99_s"] * 1e3, 1),
@@ -478,9 +478,9 @@ def bench_served_compare(torch, n_jobs):
     from paper_2505_05919_amd import serve
     from paper_2505_05919_amd.workloads import c5_stream
     jobs = c5_stream(n_jobs=n_jobs)
-    ps = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="all")
+    ps = serve.Server(memory_budget=32 << 30, max_slots=1024, quantum=100, keep_digest=True, schedule="all")
     s_ps = serve.summarize(ps.run(jobs, realtime=True))
-    srv = serve.Server(memory_budget=32 << 30, max_slots=512, quantum=100, keep_digest=True, schedule="srpt",
+    srv = serve.Server(memory_budget=32 << 30, max_slots=1024, quantum=100, keep_digest=True, schedule="srpt",
                        fill_cells=1 << 24)
     recs = srv.run(jobs, realtime=True)
     s = serve.summarize(recs)
