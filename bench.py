@@ -36,9 +36,10 @@ ALU_OPS_PER_UPDATE = 34
 # a 32-bit label per bond index written + read)
 SW_ALG_BYTES_PER_CELL = 40
 SW_COUNTERS_FILE = os.path.join(ROOT, "profiles", "sw_step_L1414_counters.json")
-SW_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "sw_step.h")]
+SW_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "sw_step.h", "cvf_internal.h")]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "met_colour_L4096_counters.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f) for f in ("philox.h", "met_sweep.h", "met_launch.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2505_05919_amd", "csrc", f)
+               for f in ("philox.h", "met_sweep.h", "met_launch.h", "cvf_internal.h")]
 
 
 def log(*a):

@@ -116,8 +116,8 @@ int cvf_params_from_si(double T_kelvin, double P_MPa, cvf_params *out);
  * acceptance table.  Swendsen-Wang (Sec. II.D) adds the state of its
  * labelling -- the paper's bond array and label array of every bond index
  * -- as 25 bytes per cell (uint32 labels and uint16 tile-local roots of the
- * 4N bond indices, one bond mask byte per cell) and 872 bytes per 64 x
- * 32-cell tile (edge bytes, the words two tiles exchange for the links
+ * 4N bond indices, one bond mask byte per cell) and 728 bytes per 64 x
+ * 16-cell tile (edge bytes, the words two tiles exchange for the links
  * between them, arrival counters).  Host only.  CVF_EINVAL for a NULL
  * argument, invalid parameters or an empty algo_mask. */
 int cvf_workspace_bytes(const cvf_params *p, int algo_mask, size_t *bytes);
@@ -169,7 +169,7 @@ int cvf_sw_steps(cvf_state *st, int64_t nsteps, void *stream);
  * cvf_observables) -- the same results as that sequence, bit for bit.  No
  * caller workspace: the chain's scalars, counter slots, tables, labels, bond
  * masks and tile roots live in a fixed device array inside the library
- * (about 6.3 MB on every GPU it runs on, held until the process ends), so
+ * (about 6.4 MiB on every GPU it runs on, held until the process ends), so
  * L <= 512; CVF_ENOMEM for a larger L.  The call allocates nothing (no
  * hipMalloc/hipFree, no host allocation).  d_sigma: 4*L*L bytes of device
  * memory, 4-byte aligned, filled from Philox stream INIT unless

@@ -27,7 +27,7 @@ constexpr int kSlots = 256;
 // fused recount, the old sigma of the facing arm across the right edge (kTH
 // bytes, one per row) and across the bottom edge (kTW bytes, one per column).
 #ifndef CVF_SW_TILE_H
-#define CVF_SW_TILE_H 32
+#define CVF_SW_TILE_H 16
 #endif
 constexpr uint32_t kTW = 64, kTH = CVF_SW_TILE_H, kTC = kTW * kTH;
 constexpr uint32_t kTT = kTC / 4;        // threads of a tile workgroup: 4 cells, 16 bond indices each

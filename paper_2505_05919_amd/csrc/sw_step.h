@@ -219,8 +219,7 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t L, uint32_t bx, uint32_t 
 // XCDs.  Instead the j-th workgroup of an XCD takes tile 32 (8 (j / 32) +
 // xcd) + j % 32, so each XCD works on runs of 32 consecutive tiles and
 // shares lines with other XCDs only at the ends of its runs.  The last
-// n % 256 tiles (the ragged last tile row, which runs after the first
-// round when there are more tiles than workgroup slots) keep their place.
+// n % 256 tiles, which do not fill a run on every XCD, keep their place.
 __device__ __forceinline__ TileGeom grid_tile(uint32_t L)
 {
     constexpr uint32_t kXcd = 8, kRun = 32;

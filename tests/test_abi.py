@@ -48,12 +48,12 @@ def test_workspace_bytes(cvf):
     met = cvf.cvf_workspace_bytes(p, cvf.CVF_ALGO_METROPOLIS)
     both = cvf.cvf_workspace_bytes(p, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
     N = 1414 * 1414
-    tiles = ((1414 + 63) // 64) * ((1414 + 31) // 32)
+    tiles = ((1414 + 63) // 64) * ((1414 + 15) // 16)
     assert met < 8192
-    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell; per 64x32
-    # tile 96 edge bytes, 192 exchange words and 2 edge counters (872 B)
-    assert both - met >= 25 * N + 872 * tiles
-    assert both - met < 25 * N + 872 * tiles + 6 * 256
+    # labels 16 B + tile-local roots 8 B + bond mask 1 B per cell; per 64x16
+    # tile 80 edge bytes, 160 exchange words and 2 edge counters (728 B)
+    assert both - met >= 25 * N + 728 * tiles
+    assert both - met < 25 * N + 728 * tiles + 6 * 256
 
 
 @pytest.mark.parametrize("field,value", [("L", 1), ("L", 0), ("L", 32768), ("q", 1), ("q", 7),
