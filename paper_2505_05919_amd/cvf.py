@@ -296,9 +296,19 @@ class Batch:
         nbytes = cvf_batch_desc_bytes(len(self.chains))
         self.desc = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream
+        self.uploaded = None
+        ts = (torch.cuda.current_stream() if stream is None else
+              stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream)))
+        # the kernels read desc on that stream: its block is not handed out
+        # again before the stream has passed them
+        self.desc.record_stream(ts)
         if nowait:
             self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
             self.h = cvf_batch_create_async([c.h for c in self.chains], self.desc, self.staging, stream)
+            # the pinned staging buffer is read by a copy on the stream that
+            # the host allocator does not know of: close() waits for it
+            self.uploaded = torch.cuda.Event()
+            self.uploaded.record(ts)
         else:
             self.h = cvf_batch_create([c.h for c in self.chains], self.desc, stream)
 
@@ -317,6 +327,11 @@ class Batch:
         return cvf_batch_autotune(self.h, sweeps, self.stream)
 
     def close(self):
+        """Destroys the handle; with nowait, first waits until the descriptor
+        upload has read the staging buffer (long done in normal use)."""
+        if getattr(self, "uploaded", None) is not None:
+            self.uploaded.synchronize()
+            self.uploaded = None
         if getattr(self, "h", None) is not None:
             cvf_batch_destroy(self.h)
             self.h = None
@@ -340,6 +355,12 @@ class Chain:
         self.sigma = sigma if sigma is not None else torch.empty(4 * self.N, dtype=torch.uint8, device="cuda")
         self.work = torch.empty(cvf_workspace_bytes(self.p, algo_mask), dtype=torch.uint8, device="cuda")
         self.stream = stream
+        if stream is not None:
+            # the kernels use both buffers on that stream: their blocks are
+            # not handed out again before the stream has passed them
+            ts = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream))
+            self.sigma.record_stream(ts)
+            self.work.record_stream(ts)
         self.h = cvf_init(self.p, self.sigma, self.work, stream)
 
     def metropolis(self, n):

@@ -143,6 +143,12 @@ class Chain3:
         self.eta = eta if eta is not None else torch.empty(3 * self.N, dtype=torch.uint8, device="cuda")
         self.work = torch.empty(cvf3_workspace_bytes(self.p, algo_mask), dtype=torch.uint8, device="cuda")
         self.stream = stream
+        if stream is not None:
+            # the kernels use these buffers on that stream: their blocks are
+            # not handed out again before the stream has passed them
+            ts = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream))
+            for t in (self.sigma, self.eta, self.work):
+                t.record_stream(ts)
         self.h = cvf3_init(self.p, self.sigma, self.eta, self.work, stream, algo_mask)
 
     def steps(self, n):
