@@ -538,9 +538,11 @@ int batch_upload(cvf_batch* b, hipStream_t s, uint8_t* staging)
         e.upr = e.la.quad ? Lc / 4 : Lc / 2;
         e.upr_inv = 1.0 / (double)e.upr;
         e.units = e.upr * (Lc / 2);
-        // rows per lane (the tuned parameter) = 2 rows per unit
+        // the tuned parameter: a quad lane moves `rows` rows (rows / 2 units of
+        // two rows, 8 rows updates); a column-pair lane makes as many updates
+        // with twice the units, so that every full workgroup has the same work
         const uint32_t rows = b->rows > 0 ? (uint32_t)b->rows : kBatchDefaultRows;
-        e.iters = rows / 2 < 1 ? 1 : rows / 2;
+        e.iters = e.la.quad ? (rows / 2 < 1 ? 1 : rows / 2) : rows;
         e.blocks = (uint32_t)(((uint64_t)e.units + 256ull * e.iters - 1) / (256ull * e.iters));
         b->start[c] = total;
         total += e.blocks;

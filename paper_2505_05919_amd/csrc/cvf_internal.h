@@ -148,6 +148,13 @@ struct BatchEntry {
     double upr_inv;          // 1 / upr
     uint32_t iters;          // units per lane
     uint32_t blocks;         // workgroups of this chain: ceil(units / (256 iters))
+    // The chain's step as the batched volume kernel opened it (device-written
+    // before every sweep's colour passes, which read it with the entry instead
+    // of following la.st)
+    int32_t skip;
+    int32_t theta;
+    uint32_t t_cur;
+    uint32_t pad;
 };
 
 // Launchers (cvf_kernels.hip).  Each returns the launch status.
@@ -184,7 +191,7 @@ hipError_t launch_sw_labels(const LatticeArgs& a, uint32_t* out, hipStream_t s);
 // table allows the one-compare acceptance.
 hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32_t count, uint32_t total_blocks,
                             int q, int colour, int le, hipStream_t s);
-hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s);
+hipError_t launch_volume_batch(BatchEntry* ent, uint32_t count, int mode, hipStream_t s);
 // Batched Swendsen-Wang stage: 0 tiles (bonds, in-tile unions and the
 // tile-crossing links), 2 shift + recount; start: count+1 prefix sums of the
 // per-chain tiles.

@@ -144,8 +144,9 @@ __global__ __launch_bounds__(kBlock) void sigma_init_kernel(LatticeArgs a)
 // ---------------------------------------------------------------------------
 // Executed by one full wavefront (lanes 0..63); `term` is 40 doubles of LDS.
 // Every global load is issued before the first store, so the whole move
-// costs one memory round trip.
-__device__ void volume_step(const VolArgs& a, double* term)
+// costs one memory round trip.  `out` (batches): the batch entry that also
+// receives the opened step (skip, theta, step index).
+__device__ void volume_step(const VolArgs& a, double* term, BatchEntry* out = nullptr)
 {
     const int lane = threadIdx.x & 63;
     DevState* st = a.st;
@@ -180,6 +181,7 @@ __device__ void volume_step(const VolArgs& a, double* term)
             st->n_coop = n_co;
             st->met_acc = m_acc;
             if (a.mode != kVolFold) st->skip = 1;
+            if (out) out->skip = 1;
         }
         return;
     }
@@ -222,6 +224,11 @@ __device__ void volume_step(const VolArgs& a, double* term)
     }
     st->skip = 0;
     st->t_cur = t;
+    if (out) {
+        out->skip = 0;
+        out->theta = th;
+        out->t_cur = t;
+    }
     st->t_next = t_next + 1;
     st->met_att = matt0 + a.met_att_add;
     st->met_acc = m_acc;
@@ -525,7 +532,7 @@ hipError_t launch_met_batch(const BatchEntry* ent, const uint32_t* start, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_volume_batch(const BatchEntry* ent, uint32_t count, int mode, hipStream_t s)
+hipError_t launch_volume_batch(BatchEntry* ent, uint32_t count, int mode, hipStream_t s)
 {
     volume_batch_kernel<<<count, 64, 0, s>>>(ent, mode);
     return hipGetLastError();

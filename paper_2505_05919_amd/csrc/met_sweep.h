@@ -471,15 +471,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ start, uint32_t count)
 {
     __shared__ uint2 tbl[32];
-    uint32_t lo = 0, hi = count;                           // start[count] = total workgroups
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (start[mid] <= blockIdx.x) lo = mid;
-        else hi = mid;
+    // The workgroup's chain: the number of chains whose first workgroup is at
+    // or before this one, minus one (start is ascending, start[0] = 0).  Every
+    // wavefront counts them itself, 256 entries per round of four independent
+    // loads and ballots, instead of a binary search's chain of dependent loads.
+    uint32_t nle = 0;
+    {
+        const uint32_t ln = threadIdx.x & 63;
+        for (uint32_t base = 0; base < count; base += 256) {
+            uint32_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = base + 64 * k + ln;
+                v[k] = i < count ? start[i] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nle += (uint32_t)__builtin_popcountll(__ballot(v[k] <= blockIdx.x));
+        }
     }
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(nle - 1);
     const LatticeArgs a = ent[lo].la;
-    const int skip = a.st->skip, theta = a.st->theta;
-    const uint32_t t = a.st->t_cur;
+    // the step state comes with the entry (written by the batched volume
+    // kernel), not through a second, dependent load from la.st
+    const int skip = ent[lo].skip, theta = ent[lo].theta;
+    const uint32_t t = ent[lo].t_cur;
     if (skip) return;                                      // step limit reached
     const uint32_t units = ent[lo].units, upr = ent[lo].upr, K = ent[lo].iters;
     const double upr_inv = ent[lo].upr_inv;
@@ -565,12 +580,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 
 // One wavefront per chain: fold and open the next step of every chain
 // (mode kVolMet before a Metropolis sweep, kVolSw before an SW step).
-__global__ __launch_bounds__(64) void volume_batch_kernel(const BatchEntry* __restrict__ ent, int mode)
+__global__ __launch_bounds__(64) void volume_batch_kernel(BatchEntry* __restrict__ ent, int mode)
 {
     __shared__ double term[40];
     VolArgs v = ent[blockIdx.x].va;
     v.mode = mode;
     if (mode != kVolMet) v.met_att_add = 0;
-    volume_step(v, term);
+    volume_step(v, term, ent + blockIdx.x);
 }
 
