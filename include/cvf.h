@@ -287,7 +287,7 @@ int cvf_batch_create_async(cvf_state *const *chains, int32_t count, void *d_desc
  * into work units of two rows times a column quad (L % 4 == 0) or a column
  * pair (L % 4 == 2), numbered row-pair major; a quad lane moves `rows` / 2
  * consecutive-by-64 units, i.e. `rows` rows (even, 2..32), and a column-pair
- * lane `rows` units, the same 8 `rows` updates; 0 restores the default (8).
+ * lane `rows` units, the same 8 `rows` updates; 0 restores the default (4).
  * Invalidates captured graphs.  Re-uploads the descriptor table on stream
  * and waits for the copy. */
 int cvf_batch_set_rows(cvf_batch *b, int32_t rows, void *stream);

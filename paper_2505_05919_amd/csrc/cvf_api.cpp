@@ -44,7 +44,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Rows per lane of a batched Metropolis pass before the autotuner runs.
-constexpr uint32_t kBatchDefaultRows = 8;
+constexpr uint32_t kBatchDefaultRows = 4;
 
 int validate(const cvf_params* p)
 {
