@@ -172,9 +172,20 @@ __device__ void volume_step(const VolArgs& a, double* term, BatchEntry* out = nu
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int k = 0; k < kSlots / 64; ++k) a.slots[j * kSlots + k * 64 + lane] = 0;
-    const int64_t n_hb = hb0 + wave_sum64(hb);
-    const int64_t n_co = co0 + wave_sum64(co);
-    const int64_t m_acc = macc0 + wave_sum64(ac);
+    // the three sums in one butterfly: each step's six 32-bit exchanges are
+    // issued together and waited for once
+    int64_t r[3] = {hb, co, ac};
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t x[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) x[j] = __shfl_xor(r[j], o, 64);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r[j] += x[j];
+    }
+    const int64_t n_hb = hb0 + r[0];
+    const int64_t n_co = co0 + r[1];
+    const int64_t m_acc = macc0 + r[2];
     if (a.mode == kVolFold || t_next >= stop_at) {   // fold only; at the step limit the step kernels skip
         if (lane == 0) {
             st->n_hb_raw = n_hb;
@@ -205,8 +216,17 @@ __device__ void volume_step(const VolArgs& a, double* term, BatchEntry* out = nu
     if (a.do_volume) {
         vatt += 1;
         if (inside) {
+            // all 36 shell terms read first, then added in ascending m while
+            // v' m <= 36 (v' >= 1, so the condition fails past m = 36; it is
+            // monotone in m, so the terms added and their order are those of
+            // the loop that stops at the first failing m)
+            double tm[36];
+#pragma unroll
+            for (int m = 1; m <= 36; ++m) tm[m - 1] = term[m];
             double sum = 0.0;
-            for (int m = 1; v1 * (double)m <= 36.0; ++m) sum = sum + term[m];
+#pragma unroll
+            for (int m = 1; m <= 36; ++m)
+                if (v1 * (double)m <= 36.0) sum = sum + tm[m - 1];
             const double u1 = 2.0 * sum;
             const int th1 = v1 < 2.0 ? 1 : 0;
             const double dH = (a.Nd * (u1 - u0))
