@@ -247,27 +247,44 @@ constexpr int kVolMet = 0, kVolFold = 1, kVolSw = 2;
 // draw the VOL block and the two ORD blocks at once, lanes 1..36 evaluate one
 // U_LJ shell term each; lane 0 then sums the terms in ascending shell order
 // up to the first shell beyond the cutoff (the order of lj3) and takes the
-// decisions.
+// decisions.  Every global load (slots, chain state, shell counts) is issued
+// before the first store, and the four slot sums share one butterfly.
 __global__ __launch_bounds__(64) void vol3_kernel(Lat3 a, int mode)
 {
     __shared__ double term[40];
     __shared__ uint32_t words[3][4];
     const int lane = threadIdx.x;
     Dev3State* s = a.st;
-    int64_t sl[kAcc];
+    int64_t sl[kAcc][kSlots / 64];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k)
+#pragma unroll
+        for (int j = 0; j < kSlots / 64; ++j) sl[k][j] = a.slots[k * kSlots + j * 64 + lane];
+    const uint32_t t = (uint32_t)s->t_next;
+    const int64_t t_next = s->t_next;
+    const double v0 = s->v, u0 = s->u;
+    const int th0 = s->theta;
+    const int64_t hb0 = s->n_hb_raw, co0 = s->n_coop, ma0 = s->met_acc, ea0 = s->eta_acc;
+    const int64_t matt0 = s->met_att, eatt0 = s->eta_att, vatt0 = s->vol_att, vacc0 = s->vol_acc;
+    const double r3 = (lane >= 1 && lane <= 36) ? a.tab->r3[lane] : 0.0;
+    int64_t r[kAcc];
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) {
-        sl[k] = 0;
+        r[k] = 0;
 #pragma unroll
         for (int j = 0; j < kSlots / 64; ++j) {
-            sl[k] += a.slots[k * kSlots + j * 64 + lane];
+            r[k] += sl[k][j];
             a.slots[k * kSlots + j * 64 + lane] = 0;
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sl[k] += __shfl_xor(sl[k], o, 64);
     }
-    const uint32_t t = (uint32_t)s->t_next;
-    const double v0 = s->v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t x[kAcc];
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) x[k] = __shfl_xor(r[k], o, 64);
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) r[k] += x[k];
+    }
     if (mode != kVolFold && lane < 3) {
         const uint4 w = philox(0u, t, lane == 2 ? 1u : 0u, lane == 0 ? kVol : kOrd, a.key0, a.key1);
         words[lane][0] = w.x;
@@ -285,36 +302,44 @@ __global__ __launch_bounds__(64) void vol3_kernel(Lat3 a, int mode)
         if (inside && lane >= 1 && lane <= 36) {
             const double d6 = (v1 * v1) * (double)(lane * lane * lane);
             const double s6 = 1.0 / d6;
-            term[lane] = d6 <= 46656.0 ? a.tab->r3[lane] * (s6 * s6 - s6) : 0.0;
+            term[lane] = d6 <= 46656.0 ? r3 * (s6 * s6 - s6) : 0.0;
         }
     }
     __syncthreads();
     if (lane != 0) return;
-    s->n_hb_raw += sl[0];
-    s->n_coop += sl[1];
-    s->met_acc += sl[2];
-    s->eta_acc += sl[3];
+    const int64_t n_hb = hb0 + r[0];
+    s->n_hb_raw = n_hb;
+    s->n_coop = co0 + r[1];
+    s->met_acc = ma0 + r[2];
+    s->eta_acc = ea0 + r[3];
     if (mode == kVolFold) return;
     if (a.do_volume) {
-        s->vol_att += 1;
+        s->vol_att = vatt0 + 1;
         if (inside) {
+            // all 36 terms read first, then added in ascending m while within
+            // the cutoff: the condition is monotone in m, so the terms added
+            // and their order are those of the loop that stops at the first
+            // shell beyond it
+            double tm[36];
+#pragma unroll
+            for (int m = 1; m <= 36; ++m) tm[m - 1] = term[m];
             double sum = 0.0;
+#pragma unroll
             for (int m = 1; m <= 36; ++m) {
                 const double d6 = (v1 * v1) * (double)(m * m * m);
-                if (!(d6 <= 46656.0)) break;
-                sum = sum + term[m];
+                if (d6 <= 46656.0) sum = sum + tm[m - 1];
             }
-            const double u0 = s->u, u1 = 2.0 * sum;
-            const int th0 = s->theta, th1 = v1 < 2.0 ? 1 : 0;
+            const double u1 = 2.0 * sum;
+            const int th1 = v1 < 2.0 ? 1 : 0;
             const double dH = (a.Nd * (u1 - u0)) + ((a.P * a.Nd) * (v1 - v0))
-                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)s->n_hb_raw);
+                            + (((double)(th1 - th0) * (a.P * a.vHB - a.J)) * (double)n_hb);
             bool acc = dH <= 0.0;
             if (!acc) acc = ((double)words[0][1] + 0.5) * (1.0 / 4294967296.0) < exp(-a.beta * dH);
             if (acc) {
                 s->v = v1;
                 s->u = u1;
                 s->theta = th1;
-                s->vol_acc += 1;
+                s->vol_acc = vacc0 + 1;
             }
         }
     }
@@ -329,9 +354,9 @@ __global__ __launch_bounds__(64) void vol3_kernel(Lat3 a, int mode)
     }
     for (int i = 0; i < 6; ++i) s->order[i] = ord[i];
     s->t_cur = t;
-    s->t_next += 1;
-    if (mode == kVolMet) s->met_att += 6 * (int64_t)a.N;
-    s->eta_att += a.N / 4;
+    s->t_next = t_next + 1;
+    if (mode == kVolMet) s->met_att = matt0 + 6 * (int64_t)a.N;
+    s->eta_att = eatt0 + a.N / 4;
 }
 
 // ---------------------------------------------------------------------------
