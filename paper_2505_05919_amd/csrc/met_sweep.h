@@ -312,7 +312,12 @@ __device__ __forceinline__ void met_table(const LatticeArgs& a, uint2* tbl, int 
 
 __device__ __forceinline__ void met_reduce(uint32_t wsum, int64_t* slots, uint32_t slot)
 {
-    // unpack the per-lane sums: wsum = sum dc + 2^10 sum dh + 2^20 accepted
+    // unpack the per-lane sums: wsum = sum dc + 2^10 sum dh + 2^20 accepted.
+    // Exact while the 10-bit fields hold the sums: a cell's four moves change
+    // N_sigma of its six arm pairs by at most 6 and N_HB_raw of its four links
+    // by at most 4 in all, so |sum dc| <= 6 and |sum dh| <= 4 per cell, and a
+    // lane moves at most 64 cells per launch (32 rows of a column quad, or 64
+    // rows of a column pair): |sum dc| <= 384, |sum dh| <= 256, accepted <= 256.
     const int ws = (int)wsum;
     const int sdc = (ws << 22) >> 22;
     const int r1v = (ws - sdc) >> 10;
