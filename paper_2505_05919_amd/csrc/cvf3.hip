@@ -1071,8 +1071,12 @@ __global__ __launch_bounds__(kBlock) void sw3_union_kernel(Lat3 a, uint32_t tx_,
 
 // Every bond index gets its root (the smallest index of its cluster), and
 // shifts by pick(word 0 of Philox(root, t, 0, SWF), q), NONE -> 0.
+// Workgroup 0 also clears the recount accumulators for the recount that
+// follows (nothing in this launch reads them).
 __global__ __launch_bounds__(kBlock) void sw3_flip_kernel(Lat3 a)
 {
+    if (blockIdx.x == 0)
+        for (uint32_t j = threadIdx.x; j < (uint32_t)(kRc * kSlots); j += kBlock) a.rc[j] = 0;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= 6 * a.N) return;
     const uint32_t r = uf_find(a.par, i);
@@ -1578,8 +1582,7 @@ int cvf3_sw_steps(cvf3_state* st, int64_t nsteps, void* stream)
         }
         t_end(st, CVF3_K_SW_UNION, s);
         t_begin(st, CVF3_K_SW_FLIP, s);
-        sw3_flip_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);
-        zero_kernel<<<1, kBlock, 0, s>>>(a.rc, kRc * kSlots);
+        sw3_flip_kernel<<<blocks_for(6ull * a.N), kBlock, 0, s>>>(a);    // also clears the recount's accumulators
         recount3_kernel<<<blocks_for(a.N), kBlock, 0, s>>>(a);
         sw3_finish_kernel<<<1, kBlock, 0, s>>>(a);
         t_end(st, CVF3_K_SW_FLIP, s);

@@ -456,6 +456,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     met_reduce(wsum, a.slots, blockIdx.x + blockIdx.y * gridDim.x);
 }
 
+// The chain c of workgroup b in a batched launch: start[c] <= b < start[c + 1]
+// (start ascending, start[0] = 0), i.e. the number of chains whose first
+// workgroup is at or before b, minus one.  Every wavefront counts them itself,
+// 256 entries per round of four independent loads and ballots, instead of a
+// binary search's chain of dependent loads.
+__device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t count, uint32_t b)
+{
+    const uint32_t ln = threadIdx.x & 63;
+    uint32_t nle = 0;
+    for (uint32_t base = 0; base < count; base += 256) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t i = base + 64 * k + ln;
+            v[k] = i < count ? start[i] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nle += (uint32_t)__builtin_popcountll(__ballot(v[k] <= b));
+    }
+    return __builtin_amdgcn_readfirstlane(nle - 1);
+}
+
 // ---------------------------------------------------------------------------
 // Batched colour pass: many independent chains of uneven L in one launch.
 // Workgroup b belongs to the chain c with start[c] <= b < start[c+1].
@@ -476,25 +498,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     const BatchEntry* __restrict__ ent, const uint32_t* __restrict__ start, uint32_t count)
 {
     __shared__ uint2 tbl[32];
-    // The workgroup's chain: the number of chains whose first workgroup is at
-    // or before this one, minus one (start is ascending, start[0] = 0).  Every
-    // wavefront counts them itself, 256 entries per round of four independent
-    // loads and ballots, instead of a binary search's chain of dependent loads.
-    uint32_t nle = 0;
-    {
-        const uint32_t ln = threadIdx.x & 63;
-        for (uint32_t base = 0; base < count; base += 256) {
-            uint32_t v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t i = base + 64 * k + ln;
-                v[k] = i < count ? start[i] : 0xFFFFFFFFu;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) nle += (uint32_t)__builtin_popcountll(__ballot(v[k] <= blockIdx.x));
-        }
-    }
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(nle - 1);
+    const uint32_t lo = batch_chain(start, count, blockIdx.x);
     const LatticeArgs a = ent[lo].la;
     // the step state comes with the entry (written by the batched volume
     // kernel), not through a second, dependent load from la.st

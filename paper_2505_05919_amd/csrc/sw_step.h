@@ -776,20 +776,9 @@ __global__ __launch_bounds__(kTT) void sw_labels_kernel(LatticeArgs a, uint32_t*
 // ---------------------------------------------------------------------------
 // Batched Swendsen-Wang: the tiled step of every chain of a batch, one launch
 // per stage.  Workgroup b belongs to the chain c with start[c] <= b <
-// start[c+1] (prefix sums of per-chain tiles, or of edge workgroups) and does
+// start[c+1] (prefix sums of per-chain tiles) and does
 // exactly what the workgroup of that chain's own launch does.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t batch_chain(const uint32_t* start, uint32_t count, uint32_t b)
-{
-    uint32_t lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (start[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // Tile of workgroup b of a batch whose chain's tiles are start .. end - 1:
 // the XCD-aware order of grid_tile over the workgroups from the first
 // multiple of 256 at or after start, in whole groups of 256 (so that
