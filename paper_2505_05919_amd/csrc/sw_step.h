@@ -212,23 +212,27 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t L, uint32_t bx, uint32_t 
     return g;
 }
 
-// The tile of this workgroup in a single-chain launch (grid = tiles).
-// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b % 8),
-// each with its own L2, and a tile row of one plane is 64 bytes, half an L2
-// line: with tiles in row-major order every line would be fetched by two
-// XCDs.  Instead the j-th workgroup of an XCD takes tile 32 (8 (j / 32) +
-// xcd) + j % 32, so each XCD works on runs of 32 consecutive tiles and
-// shares lines with other XCDs only at the ends of its runs.  The last
-// n % 256 tiles, which do not fill a run on every XCD, keep their place.
+// XCD-aware tile order.  Workgroups are dealt to the eight XCDs in turn
+// (workgroup b to XCD b % 8), each with its own L2, and a tile row of one
+// plane is 64 bytes, half an L2 line: with tiles in row-major order every
+// line would be fetched by two XCDs.  Instead the j-th workgroup of an XCD
+// takes tile kTileRun (8 (j / kTileRun) + xcd) + j % kTileRun, so each XCD
+// works on runs of kTileRun consecutive tiles and shares lines with other
+// XCDs only at the ends of its runs (runs of 8 measured best for 64 x 16
+// tiles at L = 1414, against 2, 4, 16, 32 and 64).
+constexpr uint32_t kTileXcd = 8, kTileRun = 8;
+
+// The tile of this workgroup in a single-chain launch (grid = tiles), in the
+// XCD-aware order; the last n % (8 kTileRun) tiles, which do not fill a run
+// on every XCD, keep their place.
 __device__ __forceinline__ TileGeom grid_tile(uint32_t L)
 {
-    constexpr uint32_t kXcd = 8, kRun = 32;
     const uint32_t ncx = gridDim.x, n = ncx * gridDim.y;
     const uint32_t b = blockIdx.x + blockIdx.y * ncx;
     uint32_t tile = b;
-    if (b < n - n % (kXcd * kRun)) {
-        const uint32_t xcd = b % kXcd, j = b / kXcd;
-        tile = ((j / kRun) * kXcd + xcd) * kRun + j % kRun;
+    if (b < n - n % (kTileXcd * kTileRun)) {
+        const uint32_t xcd = b % kTileXcd, j = b / kTileXcd;
+        tile = ((j / kTileRun) * kTileXcd + xcd) * kTileRun + j % kTileRun;
     }
     const uint32_t by = tile / ncx;
     return tile_geom(L, tile - by * ncx, by, ncx);
@@ -781,17 +785,17 @@ __global__ __launch_bounds__(kTT) void sw_labels_kernel(LatticeArgs a, uint32_t*
 // ---------------------------------------------------------------------------
 // Tile of workgroup b of a batch whose chain's tiles are start .. end - 1:
 // the XCD-aware order of grid_tile over the workgroups from the first
-// multiple of 256 at or after start, in whole groups of 256 (so that
-// b % 8 is the XCD there too); row-major order elsewhere.
+// multiple of 8 kTileRun at or after start, in whole groups of 8 kTileRun
+// (so that b % 8 is the XCD there too); row-major order elsewhere.
 __device__ __forceinline__ TileGeom batch_tile(const LatticeArgs& a, uint32_t b, uint32_t start, uint32_t end)
 {
-    constexpr uint32_t kXcd = 8, kRun = 32, kGroup = kXcd * kRun;
+    constexpr uint32_t kGroup = kTileXcd * kTileRun;
     const uint32_t ncx = (a.L + kTW - 1) / kTW;
     const uint32_t s8 = (start + kGroup - 1) / kGroup * kGroup;
     uint32_t tile = b - start;
     if (b >= s8 && end >= s8 && b < s8 + (end - s8) / kGroup * kGroup) {
-        const uint32_t r = b - s8, xcd = r % kXcd, j = r / kXcd;
-        tile = s8 - start + ((j / kRun) * kXcd + xcd) * kRun + j % kRun;
+        const uint32_t r = b - s8, xcd = r % kTileXcd, j = r / kTileXcd;
+        tile = s8 - start + ((j / kTileRun) * kTileXcd + xcd) * kTileRun + j % kTileRun;
     }
     const uint32_t by = tile / ncx;
     return tile_geom(a.L, tile - by * ncx, by, ncx);
