@@ -148,6 +148,30 @@ def test_batch_sw_equals_alone(cvf):
         ch.close()
 
 
+def test_batch_of_many_chains(cvf):
+    """More chains than one round of the workgroups' chain search covers
+    (256 prefix-sum entries per round), Metropolis and SW batches."""
+    rng = np.random.default_rng(17)
+    jobs = [(int(2 * rng.integers(1, 20)), 270.0 + 60.0 * rng.random(), 50.0 * rng.random(), 900 + k)
+            for k in range(300)]
+    say(f"case batch of {len(jobs)} chains, L {min(j[0] for j in jobs)}..{max(j[0] for j in jobs)}")
+    alone = []
+    for L, T, P, s in jobs:
+        ch = cvf.Chain(params(cvf, L, T, P, s))
+        ch.metropolis(3).sw(2)
+        alone.append((digest(ch), ch.obs()))
+        ch.close()
+    chains = [cvf.Chain(params(cvf, L, T, P, s)) for L, T, P, s in jobs]
+    b = cvf.Batch(chains)
+    b.metropolis(3).sw(2)
+    for k, ch in enumerate(chains):
+        assert digest(ch) == alone[k][0], (k, jobs[k])
+        assert ch.obs() == alone[k][1], (k, jobs[k])
+    b.close()
+    for ch in chains:
+        ch.close()
+
+
 def test_batch_sw_vs_oracle(cvf, oracle_mod):
     jobs = [(2, 300.0, 0.1, 31), (10, 270.0, 50.0, 32), (34, 330.0, 3000.0, 33)]
     chains, orcs = [], []
