@@ -374,7 +374,13 @@ def bench_batched(torch, cvf, sweeps, with_alone=True):
         c.close()
     v_batch = upd_per_sweep * timed_sweeps / t_batch / 1e9
     out = {"replicas": len(jobs), "sweeps": sweeps, "timed_sweeps": timed_sweeps, "graph_block": block,
-           "rows": rows, "updates_per_ns": round(v_batch, 1), "ms": round(t_batch * 1e3, 2)}
+           "rows": rows, "updates_per_ns": round(v_batch, 1), "ms": round(t_batch * 1e3, 2),
+           # whole sweeps (volume and both colour launches), 2 algorithmic bytes and
+           # the 34-op floor per update, as the single-chain roofline
+           "roofline": {"bound": "hbm", "achieved": round(2 * v_batch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(2 * v_batch / HBM_PEAK_GBS, 4), "alg_bytes_per_update": 2,
+                        "alu_frac": round(v_batch * 1e9 * ALU_OPS_PER_UPDATE / 1e12 / VALU_PEAK_TOPS, 4),
+                        "basis": "wall time of the timed sweeps"}}
     gold_path = os.path.join(ROOT, "tests", "golden", "c4_replicas.json")
     if os.path.exists(gold_path) and sweeps == 1000:
         with open(gold_path) as f:
