@@ -194,6 +194,16 @@ def test_c3_full_size_sw(cvf, oracle_mod):
     run_pair(cvf, oracle_mod, op, [("sw", 2)], labels=True)
 
 
+@pytest.mark.parametrize("L,P", [(1602, 25.0), (2048, 0.1)])
+def test_sw_parity_more_tiles_than_one_round(cvf, oracle_mod, L, P):
+    """More 64 x 16 tiles than the GPU holds at once (2626 and 4096 tiles
+    against 2048 resident workgroups), so that the tile-crossing unions pair
+    tiles of different dispatch rounds; 1602 leaves a ragged last tile column
+    and row."""
+    op = oracle_mod.params_from_si(300.0, P, L=L, seed=31)
+    run_pair(cvf, oracle_mod, op, [("sw", 2), ("met", 1), ("sw", 1)], labels=True)
+
+
 def test_determinism(cvf, oracle_mod):
     op = oracle_mod.params_from_si(300.0, 0.1, L=512, seed=77)
     res = []
