@@ -413,6 +413,40 @@ def bench_batched(torch, cvf, sweeps, with_alone=True):
     return out
 
 
+def bench_sizes(torch, cvf):
+    """One chain per lattice size (300 K, 0.1 MPa), single stream: time per
+    Metropolis sweep (L 256..16384) and per SW step (L 256..4096), each after
+    0.3 s of warm-up load, so that where a step is launch latency and where it
+    is throughput shows."""
+    def per_step(fn, n):
+        fn(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.3:
+            fn(10)
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(n)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    out = {"met": {}, "sw": {}}
+    for L in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        ch = make_chain(cvf, L, 300.0, 0.1, 12, cvf.CVF_ALGO_METROPOLIS)
+        dt = per_step(lambda k: ch.metropolis(k), min(2000, max(20, int(2e9 / (4 * L * L)))))
+        out["met"][str(L)] = {"us_per_sweep": round(dt * 1e6, 2), "updates_per_ns": round(4 * L * L / dt / 1e9, 1)}
+        assert ch.obs()["consistent"] == 1
+        ch.close()
+    for L in (256, 512, 1024, 1414, 2048, 4096):
+        ch = make_chain(cvf, L, 300.0, 0.1, 15, cvf.CVF_ALGO_METROPOLIS | cvf.CVF_ALGO_SW)
+        dt = per_step(lambda k: ch.sw(k), min(2000, max(20, int(2e8 / (L * L)))))
+        out["sw"][str(L)] = {"us_per_step": round(dt * 1e6, 2), "steps_per_s": round(1.0 / dt, 1),
+                             "cell_steps_per_ns": round(L * L / dt / 1e9, 2)}
+        assert ch.obs()["consistent"] == 1
+        ch.close()
+    return out
+
+
 def bench_served(torch, n_jobs, compare_jobs):
     """The served stream: Poisson arrivals at 200 jobs/s, L log-uniform 32..2048,
     T ~ U(270, 330) K, P ~ U(0, 50) MPa, nsteps ~ U[100, 10^4], 80 % Metropolis /
@@ -541,6 +575,8 @@ def main():
     ap.add_argument("--skip-autocorr", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-cvf3", action="store_true")
+    ap.add_argument("--sizes", action="store_true",
+                    help="also time one chain per lattice size (Metropolis L 256..16384, SW L 256..4096)")
     ap.add_argument("--skip-concurrent", action="store_true",
                     help="skip the three-stream Metropolis leg (profiled runs: it overlaps launches)")
     ap.add_argument("--cvf3-steps", type=int, default=200)
@@ -731,6 +767,11 @@ def main():
         batched = bench_batched(torch, cvf, args.batch_sweeps)
         log(f"batched: {batched}")
 
+    sizes = None
+    if args.sizes:
+        sizes = bench_sizes(torch, cvf)
+        log(f"sizes: {sizes}")
+
     served = None
     if args.serve_jobs > 0:
         served = bench_served(torch, args.serve_jobs, args.serve_compare_jobs)
@@ -769,6 +810,7 @@ def main():
         "autocorr": auto,
         "batched": batched,
         "served": served,
+        "sizes": sizes,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
