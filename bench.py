@@ -581,6 +581,8 @@ def main():
                     help="skip the three-stream Metropolis leg (profiled runs: it overlaps launches)")
     ap.add_argument("--cvf3-steps", type=int, default=200)
     ap.add_argument("--batch-sweeps", type=int, default=1000)
+    ap.add_argument("--skip-batch-alone", action="store_true",
+                    help="batched leg without the one-at-a-time comparison (profiled runs)")
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the served Poisson stream (0 = skip)")
     ap.add_argument("--serve-compare-jobs", type=int, default=200,
@@ -764,7 +766,7 @@ def main():
 
     batched = None
     if not args.skip_batch:
-        batched = bench_batched(torch, cvf, args.batch_sweeps)
+        batched = bench_batched(torch, cvf, args.batch_sweeps, with_alone=not args.skip_batch_alone)
         log(f"batched: {batched}")
 
     sizes = None
